@@ -1,0 +1,213 @@
+/*
+ * polymat.h - C ABI of the MI355X FFT-CONV library for truncated matrix power
+ * series and the NSPT Euler-Langevin step of the twisted Eguchi-Kawai model
+ * (arXiv:2001.02835).
+ *
+ * Series layout (all entry points): a truncated power series in g whose
+ * coefficients are N x N complex matrices (Section 2, eq. (4)) is a dense,
+ * row-major array of complex128 values (interleaved re, im doubles) of shape
+ * [ntrunc + 1][N][N]; element (k, i, j) holds entry (i, j) of the coefficient
+ * of g^k.  All operand pointers are DEVICE pointers owned by the caller and
+ * must be 16-byte aligned.
+ *
+ * Execution: every call validates its arguments on the host first.  On any
+ * validation failure it returns an error status and enqueues nothing.  On
+ * success it only enqueues kernels on `stream` (a hipStream_t, NULL = the
+ * default stream) and returns PM_OK without synchronising: results are ready
+ * when the stream reaches that point.  Calls never allocate device memory:
+ * all scratch space is the caller's `workspace` (device memory, 256-byte
+ * aligned, not overlapping any operand), sized by the matching *_size query.
+ * A device fault surfaces as PM_ERR_DEVICE on a later call or at the
+ * caller's synchronisation.  No C++ exception crosses this interface.
+ * Host-side state (none beyond constants) is thread-safe; calls that share
+ * one workspace must be ordered on one stream.
+ *
+ * Precision modes (the per-frequency products only; the transforms, their
+ * twiddles and 1/L normalisation, the rescaling and every value stored in a
+ * caller's series are FP64):
+ *   PM_PREC_FP64   - FP64 MFMA products (4 real products per complex one).
+ *   PM_PREC_FP32   - Fourier coefficients rounded to FP32, FP32 MFMA products
+ *                    with FP32 accumulation.
+ *   PM_PREC_BF16X3 - Fourier coefficients split as hi + lo with hi, lo BF16;
+ *                    hi*hi + hi*lo + lo*hi on BF16 MFMA with FP32 accumulation.
+ *
+ * Rescaling g -> s g: both operands of a product are multiplied by s^k at
+ * order k before the forward transform and the result by s^-k after the
+ * inverse one; in exact arithmetic the product is unchanged, in floating
+ * point it balances the magnitudes of the orders.  `scale` > 0 fixes s;
+ * `scale` == 0 lets the library choose s on the device from the per-order
+ * Frobenius norms of the operands; `scale` < 0 (or NaN/Inf) is invalid.
+ */
+#ifndef POLYMAT_H
+#define POLYMAT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+  PM_OK = 0,
+  PM_ERR_INVALID = 1,     /* bad size, null/misaligned pointer, overlap, bad scale */
+  PM_ERR_WORKSPACE = 2,   /* workspace smaller than the *_size query requires */
+  PM_ERR_DEVICE = 3,      /* a HIP call failed (launch error or earlier fault) */
+  PM_ERR_UNSUPPORTED = 4  /* valid request outside what is built (e.g. ntrunc > 63) */
+};
+typedef int pm_status;
+
+/* Precision modes of the per-frequency products. */
+enum { PM_PREC_FP64 = 0, PM_PREC_FP32 = 1, PM_PREC_BF16X3 = 2 };
+
+/* Operand forms in a batched problem. */
+enum {
+  PM_OP_N = 0,  /* the series itself */
+  PM_OP_C = 1   /* its Hermitian conjugate series, (X^+)^(k) = (X^(k))^+ */
+};
+
+/* Largest supported truncation order: the order-axis transform length is
+ * L = max(4, next power of two >= 2 (ntrunc + 1)) and must be <= 128. */
+#define PM_MAX_NTRUNC 63
+/* Largest supported matrix size N. */
+#define PM_MAX_N 4096
+/* Largest number of problems in one batched call. */
+#define PM_MAX_BATCH 4096
+
+/* Bump on any incompatible change of this header. */
+int polymat_abi_version(void);
+
+/* Human-readable text for a status code (static storage, never NULL). */
+const char* polymat_strerror(pm_status status);
+
+/* Transform length L used for a truncation order (0 if ntrunc is invalid). */
+int polymat_transform_length(int ntrunc);
+
+/*
+ * polymat_mul - truncated star product C = A * B (Section 2, eq. (5)):
+ *     C^(k) = sum_{l=0..k} A^(l) B^(k-l),   k = 0..ntrunc,
+ * computed by FFT-CONV (Section 2, Steps 1-5, eqs. (6)-(9)): the order axis
+ * is zero-padded to L >= 2 (ntrunc + 1), transformed per matrix entry with
+ * w = exp(+2 pi i / L), multiplied mode by mode as N x N complex matrices,
+ * transformed back with w^-1 and 1/L, and truncated to orders 0..ntrunc.
+ *
+ *   A, B, C    device complex128 [ntrunc+1][n][n].  C may alias A or B
+ *              (it is written only after both are consumed, on one stream).
+ *   n          1 <= n <= PM_MAX_N.   ntrunc: 0 <= ntrunc <= PM_MAX_NTRUNC.
+ *   precision  PM_PREC_* above.     scale: see "Rescaling" above.
+ *   workspace  >= polymat_workspace_size(n, ntrunc, precision, 1) bytes.
+ * Returns PM_OK or an error status (nothing enqueued on error).
+ */
+pm_status polymat_mul(const void* A, const void* B, void* C, int n, int ntrunc,
+                      int precision, double scale, void* workspace,
+                      size_t workspace_bytes, void* stream);
+
+/* Workspace bytes for `count` products of one shape (count >= 1), or 0 if
+ * the arguments are invalid. */
+size_t polymat_workspace_size(int n, int ntrunc, int precision, int count);
+
+/*
+ * One problem of a batched call.  C = op_a(A) * op_b(B) with op in PM_OP_*;
+ * A, B, C, n, ntrunc and scale as in polymat_mul.  The problems of one call
+ * are independent (the batching of Section 2: transforms batched over matrix
+ * entries and products batched over modes, here also over problems) and may
+ * differ in n and ntrunc.  Every A and B of the call is consumed before any C
+ * is written, so a C may alias any operand of the call; two problems must not
+ * write overlapping C (PM_ERR_INVALID).
+ */
+typedef struct {
+  const void* A;
+  const void* B;
+  void* C;
+  int n;
+  int ntrunc;
+  int op_a;
+  int op_b;
+  double scale;
+} pm_problem;
+
+/* Workspace bytes for one batched call over `problems` (host array of
+ * `count` entries), or 0 if any problem is invalid. */
+size_t polymat_batched_workspace_size(const pm_problem* problems, int count,
+                                      int precision);
+
+/*
+ * polymat_mul_batched - all problems of a host array in one set of launches
+ * (one forward-transform launch, one product launch per precision, one
+ * inverse-transform launch for the whole batch).  Same semantics per problem
+ * as polymat_mul.  1 <= count <= PM_MAX_BATCH.
+ */
+pm_status polymat_mul_batched(const pm_problem* problems, int count,
+                              int precision, void* workspace,
+                              size_t workspace_bytes, void* stream);
+
+/*
+ * polymat_forward_transform - Steps 1-2 alone (eqs. (6)-(7)), FP64:
+ *     At^(p) = sum_{k=0..ntrunc} s^k A^(k) w^{kp},  p = 0..L-1,
+ * L = polymat_transform_length(ntrunc), s = scale (> 0; no automatic mode).
+ *   A   device complex128 [ntrunc+1][n][n];  At  device complex128 [L][n][n]
+ *   (must not overlap A).  workspace: >= polymat_transform_workspace_size().
+ * Exposed so that the transform can be checked on its own and reused.
+ */
+pm_status polymat_forward_transform(const void* A, void* At, int n, int ntrunc,
+                                    double scale, void* workspace,
+                                    size_t workspace_bytes, void* stream);
+
+/*
+ * polymat_inverse_transform - Steps 4-5 alone (eqs. (9) and the truncation):
+ *     C^(k) = s^-k (1/L) sum_{p=0..L-1} Ct^(p) w^{-kp},  k = 0..ntrunc.
+ *   Ct  device complex128 [L][n][n];  C  device complex128 [ntrunc+1][n][n]
+ *   (must not overlap Ct).  workspace: >= polymat_transform_workspace_size().
+ */
+pm_status polymat_inverse_transform(const void* Ct, void* C, int n, int ntrunc,
+                                    double scale, void* workspace,
+                                    size_t workspace_bytes, void* stream);
+
+/* Workspace bytes of polymat_forward_transform / polymat_inverse_transform
+ * (a small table of s^k factors). */
+size_t polymat_transform_workspace_size(void);
+
+/*
+ * NSPT Euler-Langevin step of the four-dimensional TEK model (Section 2,
+ * eqs. (1)-(3)), for `replicas` independent chains at once.
+ *
+ * Twist: z_{mu nu} = exp(2 pi i k / L) for mu < nu, z_{nu mu} = conj(z_{mu nu}).
+ * With every product the truncated star product, for each replica and mu:
+ *   S_mu   = U_mu * sum_{nu != mu} ( z_{mu nu} U_nu * U_mu^+ * U_nu^+
+ *                                  + z_{mu nu}^* U_nu^+ * U_mu^+ * U_nu )
+ *   F^(k)  = i [ D^(k) - Tr(D^(k))/N ],  D = S_mu - S_mu^+   (every order k)
+ *   X^(k)  = eps F^(k) + delta_{k,1} sqrt(2 eps) eta_mu,   X^(0) = 0
+ *   U_mu  <- exp(i X) * U_mu,  exp(Y) = sum_{m=0..ntrunc} Y^{*m} / m!
+ * All four directions are updated from the old links.  The plus sign of the
+ * second staple term, the beta absorbed into the rescaled time step and the
+ * dropped order-0 drift are this library's reading of eqs. (2)-(3).
+ */
+typedef struct {
+  int n;        /* N = L * L */
+  int L;        /* twist lattice size (odd) */
+  int k;        /* twist flux */
+  int ntrunc;   /* truncation order */
+  double eps;   /* rescaled Langevin time step (> 0) */
+} nspt_params;
+
+/* Workspace bytes for nspt_langevin_step, or 0 if invalid. */
+size_t nspt_workspace_size(int replicas, const nspt_params* params, int precision);
+
+/*
+ *   U    device complex128 [replicas][4][ntrunc+1][n][n], updated in place
+ *        (order 0 is left unchanged).
+ *   eta  device complex128 [replicas][4][n][n]: Hermitian traceless noise.
+ *   precision applies to the per-frequency products; U stays FP64.
+ * The product rescaling is chosen on the device once per call from the
+ * norms of U.
+ */
+pm_status nspt_langevin_step(void* U, const void* eta, int replicas,
+                             const nspt_params* params, int precision,
+                             void* workspace, size_t workspace_bytes,
+                             void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLYMAT_H */

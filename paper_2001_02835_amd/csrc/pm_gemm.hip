@@ -1,0 +1,237 @@
+// Mode-wise complex matrix products (FFT-CONV Step 3, eq. (8)) on MFMA.
+//
+// For every product job and every mode p < L:
+//     Ct^(p) = opA(At)^(p) * opB(Bt)^(p)
+// where a plain operand X reads mode p of its transform and a conjugated
+// operand (the series X^+) reads mode (L - p) mod L conjugate-transposed:
+// the transform of X^+ at mode p is (Xt^(-p))^+, so X^+ costs no extra pass.
+//
+// Coefficients are interleaved complex (re, im) in FP64 or FP32, unpadded
+// N x N row-major per mode.  A complex product is four real MFMA products
+// (re*re - im*im, re*im + im*re).  One work-group computes a BM x BN tile of
+// one mode with WGM x WGN wavefronts of WM x WN 16x16 blocks each; K is
+// staged through double-buffered LDS in chunks of 16.  Ragged edges are
+// zero-filled on load; whole 16x16 blocks and whole k-steps of 4 that lie
+// outside the matrix are skipped.  Logical tile ids are remapped so that the
+// tiles of one mode run on one XCD and share its L2.
+#include "pm_common.h"
+#include "pm_kernels.h"
+
+namespace pm {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Cx;
+template <> struct Cx<double> {
+  using T2 = double2;
+  using Acc = d4;
+  static constexpr int kPad = 1;   // LDS row pad (elements): 65 * 16 B = 4 banks shift
+  __device__ static __forceinline__ Acc mfma(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // output element v of lane l sits at row 4 v + l / 16, column l % 16
+  __device__ static __forceinline__ int out_row(int lane, int v) { return 4 * v + lane / 16; }
+};
+template <> struct Cx<float> {
+  using T2 = float2;
+  using Acc = f4;
+  static constexpr int kPad = 2;
+  __device__ static __forceinline__ Acc mfma(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // output element v of lane l sits at row 4 (l / 16) + v, column l % 16
+  __device__ static __forceinline__ int out_row(int lane, int v) { return 4 * (lane / 16) + v; }
+};
+
+template <typename T2> __device__ __forceinline__ T2 zero2() { T2 z; z.x = 0; z.y = 0; return z; }
+template <typename T2> __device__ __forceinline__ T2 conj2(T2 v) { v.y = -v.y; return v; }
+
+template <typename T, int WM, int WN, int WGM, int WGN>
+struct GemmCfg {
+  static constexpr int BM = 16 * WM * WGM;
+  static constexpr int BN = 16 * WN * WGN;
+  static constexpr int BK = 16;
+  static constexpr int NT = kWave * WGM * WGN;
+  static constexpr int LA = (BM * BK) / NT;    // A elements loaded per thread per chunk
+  static constexpr int LB = (BK * BN) / NT;
+  static_assert((BM * BK) % NT == 0 && (BK * BN) % NT == 0, "tile/thread mismatch");
+};
+
+template <typename T, int WM, int WN, int WGM, int WGN>
+__global__ __launch_bounds__(kWave * WGM * WGN) void k_cgemm(GemmArgs args) {
+  using C = Cx<T>;
+  using T2 = typename C::T2;
+  using Acc = typename C::Acc;
+  using G = GemmCfg<T, WM, WN, WGM, WGN>;
+  constexpr int BM = G::BM, BN = G::BN, BK = G::BK, NT = G::NT;
+  constexpr int PAD = C::kPad;
+
+  __shared__ T2 As[2][BK][BM + PAD];
+  __shared__ T2 Bs[2][BK][BN + PAD];
+
+  // ---- which job, mode and tile
+  const int id = xcd_remap(blockIdx.x, gridDim.x);
+  int jidx = 0;
+  for (int j = 1; j < args.njobs; ++j)
+    if (id >= args.jobs[j].tile_begin) jidx = j;
+  const GemmJob& jb = args.jobs[jidx];
+  const int local = id - jb.tile_begin;
+  const int per_mode = jb.tiles_m * jb.tiles_n;
+  const int p = local / per_mode;
+  const int rem = local - p * per_mode;
+  const int tm = rem / jb.tiles_n;
+  const int tn = rem - tm * jb.tiles_n;
+  const int n = jb.n, L = jb.L;
+  const size_t E = static_cast<size_t>(n) * n;
+  const int pa = jb.opA ? (L - p) % L : p;
+  const int pb = jb.opB ? (L - p) % L : p;
+  const T2* __restrict__ Ag = reinterpret_cast<const T2*>(jb.A) + pa * E;
+  const T2* __restrict__ Bg = reinterpret_cast<const T2*>(jb.B) + pb * E;
+  T2* __restrict__ Cg = reinterpret_cast<T2*>(jb.C) + static_cast<size_t>(p) * E;
+  const int row0 = tm * BM, col0 = tn * BN;
+  const bool opA = jb.opA != 0, opB = jb.opB != 0;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  const int wr = wave / WGN, wc = wave - (wave / WGN) * WGN;
+  const int wrow0 = wr * 16 * WM, wcol0 = wc * 16 * WN;
+  const int li = lane & 15, lk = lane >> 4;
+
+  // ---- global -> register staging
+  T2 ra[G::LA], rb[G::LB];
+  auto load_chunk = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < G::LA; ++u) {
+      const int q = tid + NT * u;
+      int ii, kk;
+      if (!opA) { kk = q % BK; ii = q / BK; } else { ii = q % BM; kk = q / BM; }
+      const int gi = row0 + ii, gk = k0 + kk;
+      T2 v = zero2<T2>();
+      if (gi < n && gk < n) v = opA ? conj2(Ag[static_cast<size_t>(gk) * n + gi]) : Ag[static_cast<size_t>(gi) * n + gk];
+      ra[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < G::LB; ++u) {
+      const int q = tid + NT * u;
+      int jj, kk;
+      if (!opB) { jj = q % BN; kk = q / BN; } else { kk = q % BK; jj = q / BK; }
+      const int gj = col0 + jj, gk = k0 + kk;
+      T2 v = zero2<T2>();
+      if (gj < n && gk < n) v = opB ? conj2(Bg[static_cast<size_t>(gj) * n + gk]) : Bg[static_cast<size_t>(gk) * n + gj];
+      rb[u] = v;
+    }
+  };
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < G::LA; ++u) {
+      const int q = tid + NT * u;
+      int ii, kk;
+      if (!opA) { kk = q % BK; ii = q / BK; } else { ii = q % BM; kk = q / BM; }
+      As[buf][kk][ii] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < G::LB; ++u) {
+      const int q = tid + NT * u;
+      int jj, kk;
+      if (!opB) { jj = q % BN; kk = q / BN; } else { kk = q % BK; jj = q / BK; }
+      Bs[buf][kk][jj] = rb[u];
+    }
+  };
+
+  Acc cr[WM][WN], ci[WM][WN];
+#pragma unroll
+  for (int a = 0; a < WM; ++a)
+#pragma unroll
+    for (int b = 0; b < WN; ++b) { cr[a][b] = Acc{0, 0, 0, 0}; ci[a][b] = Acc{0, 0, 0, 0}; }
+
+  // wave-uniform activity of each 16x16 block (blocks fully outside the matrix are skipped)
+  bool mact[WM], nact[WN];
+#pragma unroll
+  for (int a = 0; a < WM; ++a) mact[a] = row0 + wrow0 + 16 * a < n;
+#pragma unroll
+  for (int b = 0; b < WN; ++b) nact[b] = col0 + wcol0 + 16 * b < n;
+
+  const int nchunks = (n + BK - 1) / BK;
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    const int buf = c & 1;
+    const int k0 = c * BK;
+    if (c + 1 < nchunks) load_chunk(k0 + BK);
+#pragma unroll
+    for (int s = 0; s < BK / 4; ++s) {
+      if (k0 + 4 * s < n) {
+        const int kk = 4 * s + lk;
+        T2 fa[WM], fb[WN];
+#pragma unroll
+        for (int a = 0; a < WM; ++a) fa[a] = As[buf][kk][wrow0 + 16 * a + li];
+#pragma unroll
+        for (int b = 0; b < WN; ++b) fb[b] = Bs[buf][kk][wcol0 + 16 * b + li];
+#pragma unroll
+        for (int a = 0; a < WM; ++a) {
+          const T nai = -fa[a].y;
+#pragma unroll
+          for (int b = 0; b < WN; ++b) {
+            if (mact[a] && nact[b]) {
+              cr[a][b] = C::mfma(fa[a].x, fb[b].x, cr[a][b]);
+              ci[a][b] = C::mfma(fa[a].x, fb[b].y, ci[a][b]);
+              cr[a][b] = C::mfma(nai, fb[b].y, cr[a][b]);
+              ci[a][b] = C::mfma(fa[a].y, fb[b].x, ci[a][b]);
+            }
+          }
+        }
+      }
+    }
+    if (c + 1 < nchunks) store_chunk(buf ^ 1);
+    __syncthreads();
+  }
+
+  // ---- epilogue: interleave re/im and store the tile
+#pragma unroll
+  for (int a = 0; a < WM; ++a) {
+#pragma unroll
+    for (int b = 0; b < WN; ++b) {
+      const int gj = col0 + wcol0 + 16 * b + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = row0 + wrow0 + 16 * a + C::out_row(lane, v);
+        if (gi < n && gj < n) {
+          T2 o;
+          o.x = cr[a][b][v];
+          o.y = ci[a][b][v];
+          Cg[static_cast<size_t>(gi) * n + gj] = o;
+        }
+      }
+    }
+  }
+}
+
+// Tile shapes: 64 x 64 tiles with four wavefronts of 2 x 2 blocks.
+constexpr int kWM = 2, kWN = 2, kWGM = 2, kWGN = 2;
+
+}  // namespace
+
+int gemm_tile(FourierType t) {
+  (void)t;
+  return 16 * kWM * kWGM;
+}
+
+hipError_t launch_gemm(const GemmArgs& a, FourierType t, hipStream_t s) {
+  if (a.njobs <= 0 || a.total_tiles <= 0) return hipSuccess;
+  constexpr int nt = kWave * kWGM * kWGN;
+  if (t == kF64) {
+    k_cgemm<double, kWM, kWN, kWGM, kWGN><<<a.total_tiles, nt, 0, s>>>(a);
+  } else if (t == kF32) {
+    k_cgemm<float, kWM, kWN, kWGM, kWGN><<<a.total_tiles, nt, 0, s>>>(a);
+  } else {
+    return hipErrorInvalidValue;   // the split-BF16 products live in pm_gemm_bf16.hip
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pm

@@ -1,0 +1,15 @@
+// Internal interface of the NSPT Euler-Langevin step (pm_nspt.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "polymat.h"
+
+namespace pm {
+
+size_t nspt_workspace_bytes(int replicas, const nspt_params* params, int precision);
+pm_status nspt_step(void* U, const void* eta, int replicas, const nspt_params* params, int precision,
+                    void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+}  // namespace pm

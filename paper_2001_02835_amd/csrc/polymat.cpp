@@ -1,0 +1,430 @@
+// Host runtime of the polymat library: argument validation, workspace
+// planning and the launch sequence of each C-ABI entry point.
+//
+// Nothing here allocates device memory or synchronises: every call checks its
+// arguments, carves the caller's workspace into per-product regions and
+// enqueues kernels on the caller's stream.
+#include "polymat.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "pm_common.h"
+#include "pm_kernels.h"
+#include "pm_nspt.h"
+
+namespace {
+
+using namespace pm;
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int transform_length(int ntrunc) {
+  if (ntrunc < 0 || ntrunc > PM_MAX_NTRUNC) return 0;
+  const int need = 2 * (ntrunc + 1);
+  int L = 4;
+  while (L < need) L *= 2;
+  return L;
+}
+
+FourierType fourier_type(int prec) {
+  return prec == PM_PREC_FP64 ? kF64 : (prec == PM_PREC_FP32 ? kF32 : kBF16Split);
+}
+
+// Bytes of the Fourier coefficients of one operand over L modes.
+size_t operand_bytes(int n, int L, int prec) {
+  const size_t E = static_cast<size_t>(n) * n;
+  switch (prec) {
+    case PM_PREC_FP64: return E * L * 16;
+    case PM_PREC_FP32: return E * L * 8;
+    default: return static_cast<size_t>(bf16_ld(n)) * n * 4 * 2 * L;   // four BF16 planes
+  }
+}
+// Bytes of the product coefficients over L modes (FP64 or FP32 complex).
+size_t result_bytes(int n, int L, int prec) {
+  const size_t E = static_cast<size_t>(n) * n;
+  return E * L * (prec == PM_PREC_FP64 ? 16 : 8);
+}
+
+struct ProductLayout {
+  size_t rec, partA, partB, At, Bt, Ct, total;
+};
+
+ProductLayout product_layout(int n, int ntrunc, int prec) {
+  ProductLayout l{};
+  const int L = transform_length(ntrunc);
+  const size_t part = static_cast<size_t>(ntrunc + 1) * kNormChunks * sizeof(double);
+  size_t off = 0;
+  l.rec = off;   off += align_up(sizeof(ScaleRec));
+  l.partA = off; off += align_up(part);
+  l.partB = off; off += align_up(part);
+  l.At = off;    off += align_up(operand_bytes(n, L, prec));
+  l.Bt = off;    off += align_up(operand_bytes(n, L, prec));
+  l.Ct = off;    off += align_up(result_bytes(n, L, prec));
+  l.total = off;
+  return l;
+}
+
+bool valid_prec(int p) { return p == PM_PREC_FP64 || p == PM_PREC_FP32 || p == PM_PREC_BF16X3; }
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+struct Range { uintptr_t b, e; };
+bool overlaps(Range x, Range y) { return x.b < y.e && y.b < x.e; }
+Range range_of(const void* p, size_t bytes) {
+  uintptr_t b = reinterpret_cast<uintptr_t>(p);
+  return Range{b, b + bytes};
+}
+size_t series_bytes(int n, int ntrunc) { return static_cast<size_t>(n) * n * (ntrunc + 1) * 16; }
+
+pm_status check_problem_shape(const void* A, const void* B, const void* C, int n, int ntrunc,
+                              double scale) {
+  if (!A || !B || !C) return PM_ERR_INVALID;
+  if (!aligned(A, 16) || !aligned(B, 16) || !aligned(C, 16)) return PM_ERR_INVALID;
+  if (n < 1 || n > PM_MAX_N) return PM_ERR_INVALID;
+  if (ntrunc < 0) return PM_ERR_INVALID;
+  if (ntrunc > PM_MAX_NTRUNC) return PM_ERR_UNSUPPORTED;
+  if (!std::isfinite(scale) || scale < 0.0) return PM_ERR_INVALID;
+  return PM_OK;
+}
+
+pm_status from_hip(hipError_t e) { return e == hipSuccess ? PM_OK : PM_ERR_DEVICE; }
+
+// Enqueue the whole FFT-CONV pipeline for a list of validated problems whose
+// workspace regions are given.
+struct Planned {
+  pm_problem pr;
+  int L;
+  char* ws;        // base of this product's region
+  ProductLayout lay;
+};
+
+pm_status enqueue_products(const std::vector<Planned>& items, int prec, hipStream_t st) {
+  const FourierType ft = fourier_type(prec);
+
+  // 1. per-order norms of the operands whose s is chosen on the device
+  {
+    NormArgs na{};
+    int max_nord = 0;
+    auto flush = [&]() -> pm_status {
+      if (na.njobs == 0) return PM_OK;
+      pm_status s = from_hip(launch_norms(na, max_nord, st));
+      na.njobs = 0;
+      max_nord = 0;
+      return s;
+    };
+    for (const Planned& it : items) {
+      if (it.pr.scale > 0.0) continue;
+      const int nord = it.pr.ntrunc + 1;
+      const int E = it.pr.n * it.pr.n;
+      for (int side = 0; side < 2; ++side) {
+        if (na.njobs == kMaxTransformJobs) { pm_status s = flush(); if (s) return s; }
+        NormJob& j = na.jobs[na.njobs++];
+        j.src = static_cast<const double2*>(side == 0 ? it.pr.A : it.pr.B);
+        j.partial = reinterpret_cast<double*>(it.ws + (side == 0 ? it.lay.partA : it.lay.partB));
+        j.E = E;
+        j.nord = nord;
+        max_nord = std::max(max_nord, nord);
+      }
+    }
+    pm_status s = flush();
+    if (s) return s;
+  }
+  // 2. the scale record (s^k and s^-k / L tables) of every product
+  {
+    ScaleArgs sa{};
+    for (const Planned& it : items) {
+      if (sa.njobs == kMaxTransformJobs) {
+        pm_status s = from_hip(launch_scale(sa, st));
+        if (s) return s;
+        sa.njobs = 0;
+      }
+      ScaleJob& j = sa.jobs[sa.njobs++];
+      j.partA = reinterpret_cast<const double*>(it.ws + it.lay.partA);
+      j.partB = reinterpret_cast<const double*>(it.ws + it.lay.partB);
+      j.rec = reinterpret_cast<ScaleRec*>(it.ws + it.lay.rec);
+      j.nord = it.pr.ntrunc + 1;
+      j.L = it.L;
+      j.fixed_s = it.pr.scale;
+    }
+    pm_status s = from_hip(launch_scale(sa, st));
+    if (s) return s;
+  }
+  // 3. forward transforms, one launch per transform length (and per 64 jobs)
+  std::map<int, std::vector<const Planned*>> byL;
+  for (const Planned& it : items) byL[it.L].push_back(&it);
+  for (auto& kv : byL) {
+    FwdArgs fa{};
+    int maxE = 0;
+    auto flush = [&]() -> pm_status {
+      if (fa.njobs == 0) return PM_OK;
+      pm_status s = from_hip(launch_forward(fa, kv.first, maxE, ft, st));
+      fa.njobs = 0;
+      maxE = 0;
+      return s;
+    };
+    for (const Planned* it : kv.second) {
+      for (int side = 0; side < 2; ++side) {
+        if (fa.njobs == kMaxTransformJobs) { pm_status s = flush(); if (s) return s; }
+        FwdJob& j = fa.jobs[fa.njobs++];
+        j.src = static_cast<const double2*>(side == 0 ? it->pr.A : it->pr.B);
+        j.dst = it->ws + (side == 0 ? it->lay.At : it->lay.Bt);
+        j.rec = reinterpret_cast<const ScaleRec*>(it->ws + it->lay.rec);
+        j.E = it->pr.n * it->pr.n;
+        j.nord = it->pr.ntrunc + 1;
+        j.n = it->pr.n;
+        // BF16 layout role: the factor's contracted index is its column for
+        // the left factor and its row for the right factor; a conjugated
+        // operand swaps the two.
+        const int op = side == 0 ? it->pr.op_a : it->pr.op_b;
+        j.role = (side ^ op) & 1;
+        maxE = std::max(maxE, j.E);
+      }
+    }
+    pm_status s = flush();
+    if (s) return s;
+  }
+  // 4. mode-wise products
+  {
+    GemmArgs ga{};
+    const int tile = gemm_tile(ft);
+    auto flush = [&]() -> pm_status {
+      if (ga.njobs == 0) return PM_OK;
+      pm_status s = from_hip(launch_gemm(ga, ft, st));
+      ga.njobs = 0;
+      ga.total_tiles = 0;
+      return s;
+    };
+    for (const Planned& it : items) {
+      if (ga.njobs == kMaxGemmJobs) { pm_status s = flush(); if (s) return s; }
+      GemmJob& j = ga.jobs[ga.njobs++];
+      j.A = it.ws + it.lay.At;
+      j.B = it.ws + it.lay.Bt;
+      j.C = it.ws + it.lay.Ct;
+      j.n = it.pr.n;
+      j.L = it.L;
+      j.opA = it.pr.op_a;
+      j.opB = it.pr.op_b;
+      j.tiles_m = (it.pr.n + tile - 1) / tile;
+      j.tiles_n = j.tiles_m;
+      j.tile_begin = ga.total_tiles;
+      ga.total_tiles += j.tiles_m * j.tiles_n * it.L;
+    }
+    pm_status s = flush();
+    if (s) return s;
+  }
+  // 5. inverse transforms, truncation and unscaling into C
+  for (auto& kv : byL) {
+    InvArgs ia{};
+    int maxE = 0;
+    auto flush = [&]() -> pm_status {
+      if (ia.njobs == 0) return PM_OK;
+      pm_status s = from_hip(launch_inverse(ia, kv.first, maxE, ft, st));
+      ia.njobs = 0;
+      maxE = 0;
+      return s;
+    };
+    for (const Planned* it : kv.second) {
+      if (ia.njobs == kMaxTransformJobs) { pm_status s = flush(); if (s) return s; }
+      InvJob& j = ia.jobs[ia.njobs++];
+      j.src = it->ws + it->lay.Ct;
+      j.dst = static_cast<double2*>(it->pr.C);
+      j.rec = reinterpret_cast<const ScaleRec*>(it->ws + it->lay.rec);
+      j.E = it->pr.n * it->pr.n;
+      j.nord = it->pr.ntrunc + 1;
+      maxE = std::max(maxE, j.E);
+    }
+    pm_status s = flush();
+    if (s) return s;
+  }
+  return PM_OK;
+}
+
+pm_status plan_batch(const pm_problem* problems, int count, int prec, char* ws, size_t ws_bytes,
+                     std::vector<Planned>& out, size_t* need_out) {
+  if (!problems || count < 1 || count > PM_MAX_BATCH || !valid_prec(prec)) return PM_ERR_INVALID;
+  size_t off = 0;
+  out.clear();
+  out.reserve(count);
+  for (int i = 0; i < count; ++i) {
+    const pm_problem& p = problems[i];
+    pm_status s = check_problem_shape(p.A, p.B, p.C, p.n, p.ntrunc, p.scale);
+    if (s) return s;
+    if ((p.op_a != PM_OP_N && p.op_a != PM_OP_C) || (p.op_b != PM_OP_N && p.op_b != PM_OP_C))
+      return PM_ERR_INVALID;
+    Planned it;
+    it.pr = p;
+    it.L = transform_length(p.ntrunc);
+    it.lay = product_layout(p.n, p.ntrunc, prec);
+    it.ws = ws ? ws + off : nullptr;
+    off += it.lay.total;
+    out.push_back(it);
+  }
+  if (need_out) *need_out = off;
+  if (!ws) return PM_OK;
+  if (!aligned(ws, kAlign)) return PM_ERR_INVALID;
+  if (ws_bytes < off) return PM_ERR_WORKSPACE;
+  const Range wr = range_of(ws, off);
+  for (const Planned& it : out) {
+    const size_t sb = series_bytes(it.pr.n, it.pr.ntrunc);
+    if (overlaps(wr, range_of(it.pr.A, sb)) || overlaps(wr, range_of(it.pr.B, sb)) ||
+        overlaps(wr, range_of(it.pr.C, sb)))
+      return PM_ERR_INVALID;
+  }
+  return PM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int polymat_abi_version(void) { return 1; }
+
+const char* polymat_strerror(pm_status status) {
+  switch (status) {
+    case PM_OK: return "success";
+    case PM_ERR_INVALID: return "invalid argument";
+    case PM_ERR_WORKSPACE: return "workspace too small";
+    case PM_ERR_DEVICE: return "HIP device error";
+    case PM_ERR_UNSUPPORTED: return "unsupported size or mode";
+    default: return "unknown status";
+  }
+}
+
+int polymat_transform_length(int ntrunc) { return transform_length(ntrunc); }
+
+size_t polymat_workspace_size(int n, int ntrunc, int precision, int count) {
+  if (n < 1 || n > PM_MAX_N || ntrunc < 0 || ntrunc > PM_MAX_NTRUNC || !valid_prec(precision) ||
+      count < 1 || count > PM_MAX_BATCH)
+    return 0;
+  return product_layout(n, ntrunc, precision).total * static_cast<size_t>(count);
+}
+
+size_t polymat_batched_workspace_size(const pm_problem* problems, int count, int precision) {
+  std::vector<Planned> items;
+  size_t need = 0;
+  if (plan_batch(problems, count, precision, nullptr, 0, items, &need) != PM_OK) return 0;
+  return need;
+}
+
+pm_status polymat_mul_batched(const pm_problem* problems, int count, int precision, void* workspace,
+                              size_t workspace_bytes, void* stream) {
+  if (!workspace) return PM_ERR_INVALID;
+  std::vector<Planned> items;
+  pm_status s = plan_batch(problems, count, precision, static_cast<char*>(workspace), workspace_bytes,
+                           items, nullptr);
+  if (s) return s;
+  // two problems must not write overlapping outputs
+  std::vector<Range> outs;
+  outs.reserve(items.size());
+  for (const Planned& it : items) outs.push_back(range_of(it.pr.C, series_bytes(it.pr.n, it.pr.ntrunc)));
+  std::sort(outs.begin(), outs.end(), [](const Range& a, const Range& b) { return a.b < b.b; });
+  for (size_t i = 1; i < outs.size(); ++i)
+    if (outs[i].b < outs[i - 1].e) return PM_ERR_INVALID;
+  return enqueue_products(items, precision, static_cast<hipStream_t>(stream));
+}
+
+pm_status polymat_mul(const void* A, const void* B, void* C, int n, int ntrunc, int precision,
+                      double scale, void* workspace, size_t workspace_bytes, void* stream) {
+  pm_problem p;
+  p.A = A;
+  p.B = B;
+  p.C = C;
+  p.n = n;
+  p.ntrunc = ntrunc;
+  p.op_a = PM_OP_N;
+  p.op_b = PM_OP_N;
+  p.scale = scale;
+  return polymat_mul_batched(&p, 1, precision, workspace, workspace_bytes, stream);
+}
+
+size_t polymat_transform_workspace_size(void) { return align_up(sizeof(ScaleRec)); }
+
+static pm_status transform_common(const void* X, const void* Y, int n, int ntrunc, double scale,
+                                  void* workspace, size_t workspace_bytes) {
+  if (!X || !Y || !aligned(X, 16) || !aligned(Y, 16)) return PM_ERR_INVALID;
+  if (n < 1 || n > PM_MAX_N || ntrunc < 0) return PM_ERR_INVALID;
+  if (ntrunc > PM_MAX_NTRUNC) return PM_ERR_UNSUPPORTED;
+  if (!std::isfinite(scale) || scale <= 0.0) return PM_ERR_INVALID;
+  if (!workspace || !aligned(workspace, kAlign)) return PM_ERR_INVALID;
+  if (workspace_bytes < polymat_transform_workspace_size()) return PM_ERR_WORKSPACE;
+  return PM_OK;
+}
+
+pm_status polymat_forward_transform(const void* A, void* At, int n, int ntrunc, double scale,
+                                    void* workspace, size_t workspace_bytes, void* stream) {
+  pm_status s = transform_common(A, At, n, ntrunc, scale, workspace, workspace_bytes);
+  if (s) return s;
+  const int L = transform_length(ntrunc);
+  const size_t E = static_cast<size_t>(n) * n;
+  const Range wr = range_of(workspace, polymat_transform_workspace_size());
+  if (overlaps(wr, range_of(A, series_bytes(n, ntrunc))) || overlaps(wr, range_of(At, E * L * 16)) ||
+      overlaps(range_of(A, series_bytes(n, ntrunc)), range_of(At, E * L * 16)))
+    return PM_ERR_INVALID;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  ScaleArgs sa{};
+  sa.njobs = 1;
+  sa.jobs[0].rec = static_cast<ScaleRec*>(workspace);
+  sa.jobs[0].nord = ntrunc + 1;
+  sa.jobs[0].L = L;
+  sa.jobs[0].fixed_s = scale;
+  s = from_hip(launch_scale(sa, st));
+  if (s) return s;
+  FwdArgs fa{};
+  fa.njobs = 1;
+  fa.jobs[0].src = static_cast<const double2*>(A);
+  fa.jobs[0].dst = At;
+  fa.jobs[0].rec = static_cast<const ScaleRec*>(workspace);
+  fa.jobs[0].E = n * n;
+  fa.jobs[0].nord = ntrunc + 1;
+  fa.jobs[0].n = n;
+  fa.jobs[0].role = 0;
+  return from_hip(launch_forward(fa, L, n * n, kF64, st));
+}
+
+pm_status polymat_inverse_transform(const void* Ct, void* C, int n, int ntrunc, double scale,
+                                    void* workspace, size_t workspace_bytes, void* stream) {
+  pm_status s = transform_common(Ct, C, n, ntrunc, scale, workspace, workspace_bytes);
+  if (s) return s;
+  const int L = transform_length(ntrunc);
+  const size_t E = static_cast<size_t>(n) * n;
+  const Range wr = range_of(workspace, polymat_transform_workspace_size());
+  if (overlaps(wr, range_of(C, series_bytes(n, ntrunc))) || overlaps(wr, range_of(Ct, E * L * 16)) ||
+      overlaps(range_of(C, series_bytes(n, ntrunc)), range_of(Ct, E * L * 16)))
+    return PM_ERR_INVALID;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  ScaleArgs sa{};
+  sa.njobs = 1;
+  sa.jobs[0].rec = static_cast<ScaleRec*>(workspace);
+  sa.jobs[0].nord = ntrunc + 1;
+  sa.jobs[0].L = L;
+  sa.jobs[0].fixed_s = scale;
+  s = from_hip(launch_scale(sa, st));
+  if (s) return s;
+  InvArgs ia{};
+  ia.njobs = 1;
+  ia.jobs[0].src = Ct;
+  ia.jobs[0].dst = static_cast<double2*>(C);
+  ia.jobs[0].rec = static_cast<const ScaleRec*>(workspace);
+  ia.jobs[0].E = n * n;
+  ia.jobs[0].nord = ntrunc + 1;
+  return from_hip(launch_inverse(ia, L, n * n, kF64, st));
+}
+
+size_t nspt_workspace_size(int replicas, const nspt_params* params, int precision) {
+  return pm::nspt_workspace_bytes(replicas, params, precision);
+}
+
+pm_status nspt_langevin_step(void* U, const void* eta, int replicas, const nspt_params* params,
+                             int precision, void* workspace, size_t workspace_bytes, void* stream) {
+  return pm::nspt_step(U, eta, replicas, params, precision, workspace, workspace_bytes,
+                       static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

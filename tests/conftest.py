@@ -38,3 +38,18 @@ def load_golden(name):
 @pytest.fixture
 def golden():
     return load_golden
+
+
+def pytest_collection_modifyitems(config, items):
+    """GPU tests are skipped (not passed) where no GPU is visible."""
+    try:
+        import torch
+        have_gpu = torch.cuda.is_available()
+    except Exception:  # pragma: no cover
+        have_gpu = False
+    if have_gpu:
+        return
+    skip = pytest.mark.skip(reason="no GPU visible")
+    for it in items:
+        if "gpu" in it.keywords:
+            it.add_marker(skip)

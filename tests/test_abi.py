@@ -1,0 +1,137 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/polymat.h declares, and rejects bad arguments on the host before it
+touches the device (every call below fails validation, so nothing is ever
+enqueued and no pointer is dereferenced)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2001_02835_amd as pm
+from paper_2001_02835_amd import _native as nat
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "polymat.h")
+
+# fake, 256-byte aligned "device" addresses; only ever passed to calls that
+# must fail validation
+FAKE_A, FAKE_B, FAKE_C, FAKE_WS = 0x10000000, 0x20000000, 0x30000000, 0x40000000
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", text)
+    keep = [n for n in names if n.startswith(("polymat_", "nspt_"))]
+    return sorted(set(keep))
+
+
+def test_library_loads_and_exports_every_declared_function():
+    lib = pm.lib()
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(nat.SIGNATURES), "binding and header disagree"
+    assert lib.polymat_abi_version() == 1
+
+
+def test_strerror_texts():
+    for s in range(5):
+        assert isinstance(nat.strerror(s), str) and nat.strerror(s)
+    assert nat.strerror(99) == "unknown status"
+
+
+def test_transform_length():
+    lib = pm.lib()
+    assert [lib.polymat_transform_length(t) for t in (0, 1, 3, 7, 15, 31, 63, 5, 12)] == \
+        [4, 4, 8, 16, 32, 64, 128, 16, 32]
+    assert lib.polymat_transform_length(-1) == 0
+    assert lib.polymat_transform_length(64) == 0
+
+
+def test_workspace_size_queries():
+    lib = pm.lib()
+    w1 = lib.polymat_workspace_size(225, 31, nat.PM_PREC_FP64, 1)
+    assert w1 >= 3 * 64 * 225 * 225 * 16
+    assert lib.polymat_workspace_size(225, 31, nat.PM_PREC_FP64, 4) == 4 * w1
+    assert lib.polymat_workspace_size(225, 31, nat.PM_PREC_FP32, 1) < w1
+    assert lib.polymat_workspace_size(225, 31, nat.PM_PREC_BF16X3, 1) < w1
+    for bad in [(0, 7, 0, 1), (9, -1, 0, 1), (9, 64, 0, 1), (9, 7, 3, 1), (9, 7, 0, 0), (5000, 7, 0, 1)]:
+        assert lib.polymat_workspace_size(*bad) == 0
+    assert lib.polymat_transform_workspace_size() >= 8 * 129
+
+
+def _mul(A=FAKE_A, B=FAKE_B, C=FAKE_C, n=9, nt=7, prec=0, scale=0.0, ws=FAKE_WS, wsb=0, stream=None):
+    return pm.lib().polymat_mul(A, B, C, n, nt, prec, scale, ws, wsb, stream)
+
+
+def test_polymat_mul_rejects_bad_arguments():
+    need = pm.lib().polymat_workspace_size(9, 7, 0, 1)
+    E = nat.PM_ERR_INVALID
+    assert _mul(A=None, wsb=need) == E
+    assert _mul(B=None, wsb=need) == E
+    assert _mul(C=None, wsb=need) == E
+    assert _mul(A=FAKE_A + 8, wsb=need) == E             # misaligned
+    assert _mul(n=0, wsb=need) == E
+    assert _mul(n=-3, wsb=need) == E
+    assert _mul(nt=-1, wsb=need) == E
+    assert _mul(nt=64, wsb=need) == nat.PM_ERR_UNSUPPORTED
+    assert _mul(prec=7, wsb=need) == E
+    assert _mul(scale=-1.0, wsb=need) == E
+    assert _mul(scale=float("nan"), wsb=need) == E
+    assert _mul(scale=float("inf"), wsb=need) == E
+    assert _mul(ws=None, wsb=need) == E
+    assert _mul(ws=FAKE_WS + 64, wsb=need) == E          # workspace must be 256-B aligned
+    assert _mul(wsb=need - 1) == nat.PM_ERR_WORKSPACE
+    assert _mul(ws=FAKE_A, wsb=need) == E                # workspace overlaps A
+    assert _mul(ws=FAKE_C - 256, wsb=need) == E          # workspace overlaps C
+
+
+def test_batched_rejects_bad_arguments():
+    lib = pm.lib()
+    arr = (nat.PmProblem * 2)()
+    for i in range(2):
+        arr[i].A, arr[i].B, arr[i].C = FAKE_A, FAKE_B, FAKE_C + i * 0x1000000
+        arr[i].n, arr[i].ntrunc, arr[i].op_a, arr[i].op_b, arr[i].scale = 9, 7, 0, 0, 0.0
+    need = lib.polymat_batched_workspace_size(arr, 2, 0)
+    assert need == 2 * lib.polymat_workspace_size(9, 7, 0, 1)
+    assert lib.polymat_mul_batched(arr, 0, 0, FAKE_WS, need, None) == nat.PM_ERR_INVALID
+    assert lib.polymat_mul_batched(None, 1, 0, FAKE_WS, need, None) == nat.PM_ERR_INVALID
+    assert lib.polymat_mul_batched(arr, 2, 0, FAKE_WS, need - 1, None) == nat.PM_ERR_WORKSPACE
+    arr[1].op_a = 2
+    assert lib.polymat_batched_workspace_size(arr, 2, 0) == 0
+    assert lib.polymat_mul_batched(arr, 2, 0, FAKE_WS, need, None) == nat.PM_ERR_INVALID
+    arr[1].op_a = 1
+    arr[1].C = FAKE_C + 128                                # two outputs overlap
+    assert lib.polymat_mul_batched(arr, 2, 0, FAKE_WS, need, None) == nat.PM_ERR_INVALID
+
+
+def test_transform_entry_points_reject_bad_arguments():
+    lib = pm.lib()
+    w = lib.polymat_transform_workspace_size()
+    E = nat.PM_ERR_INVALID
+    assert lib.polymat_forward_transform(FAKE_A, FAKE_B, 9, 7, 0.0, FAKE_WS, w, None) == E  # scale must be > 0
+    assert lib.polymat_forward_transform(None, FAKE_B, 9, 7, 1.0, FAKE_WS, w, None) == E
+    assert lib.polymat_forward_transform(FAKE_A, FAKE_B, 9, 7, 1.0, FAKE_WS, w - 1, None) == nat.PM_ERR_WORKSPACE
+    assert lib.polymat_forward_transform(FAKE_A, FAKE_A + 256, 9, 7, 1.0, FAKE_WS, w, None) == E  # overlap
+    assert lib.polymat_inverse_transform(FAKE_A, FAKE_B, 9, 99, 1.0, FAKE_WS, w, None) == nat.PM_ERR_UNSUPPORTED
+    assert lib.polymat_inverse_transform(FAKE_A, FAKE_B, 0, 7, 1.0, FAKE_WS, w, None) == E
+
+
+def test_nspt_rejects_bad_arguments():
+    lib = pm.lib()
+    good = nat.NsptParams(9, 3, 1, 7, 0.01)
+    for bad in [nat.NsptParams(10, 3, 1, 7, 0.01),     # n != L*L
+                nat.NsptParams(9, 3, 1, 7, -0.01),     # eps <= 0
+                nat.NsptParams(9, 3, 1, 64, 0.01),     # ntrunc too large
+                nat.NsptParams(16, 4, 1, 7, 0.01)]:    # even L
+        assert lib.nspt_workspace_size(1, ctypes.byref(bad), 0) == 0
+        assert lib.nspt_langevin_step(FAKE_A, FAKE_B, 1, ctypes.byref(bad), 0, FAKE_WS, 1 << 40, None) != nat.PM_OK
+    need = lib.nspt_workspace_size(2, ctypes.byref(good), 0)
+    assert need > 0
+    assert lib.nspt_workspace_size(0, ctypes.byref(good), 0) == 0
+    assert lib.nspt_langevin_step(FAKE_A, FAKE_B, 2, ctypes.byref(good), 0, FAKE_WS, need - 1, None) == \
+        nat.PM_ERR_WORKSPACE
+    assert lib.nspt_langevin_step(None, FAKE_B, 2, ctypes.byref(good), 0, FAKE_WS, need, None) == nat.PM_ERR_INVALID

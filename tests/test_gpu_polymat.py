@@ -1,0 +1,156 @@
+"""GPU parity of the FFT-CONV path against the FP64 oracle, through the C ABI.
+
+Inputs come from the seeded generators of `synth`; every expected value comes
+from `oracle` (the naive star product or the literal FFT-CONV steps).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import fftconv, series as ser
+import paper_2001_02835_amd as pm
+from gpu_util import DEV, TOL, order_errors, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def rs(seed, n, nt, r=1.0):
+    return synth.random_series(synth.rng_for(700, seed), n, nt, r)
+
+
+@pytest.mark.parametrize("n,nt,s", [(9, 7, 1.0), (5, 0, 1.0), (7, 3, 0.7), (17, 12, 1.3), (3, 31, 0.9), (4, 63, 1.05)])
+def test_forward_transform_matches_definition(n, nt, s):
+    a = rs(1, n, nt)
+    L = pm.transform_length(nt)
+    got = to_host(pm.forward_transform(to_dev(a), scale=s))
+    scaled = a * (s ** np.arange(nt + 1))[:, None, None]
+    ref = fftconv.forward(scaled, L)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    # both sides round: the oracle sums L terms directly (error ~ eps L), the
+    # kernel in log2(L) butterfly stages; the bound is 1e-15 L
+    assert err < 1e-15 * L, err
+
+
+@pytest.mark.parametrize("n,nt,s", [(9, 7, 1.0), (5, 0, 1.0), (6, 5, 2.0), (17, 31, 0.8), (4, 63, 1.02)])
+def test_inverse_transform_matches_definition(n, nt, s):
+    L = pm.transform_length(nt)
+    ct = synth.random_series(synth.rng_for(701, n, nt), n, L - 1)
+    got = to_host(pm.inverse_transform(to_dev(ct), nt, scale=s))
+    ref = fftconv.inverse(ct)[: nt + 1] * (s ** -np.arange(nt + 1.0))[:, None, None]
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err < 1e-15 * L, err
+
+
+def test_small_product_matches_naive_oracle():
+    # N = 9, ntrunc = 7 (transform length 16), i.i.d. N(0,1) entries
+    a, b = rs(2, 9, 7), rs(3, 9, 7)
+    c = to_host(pm.polymat_mul(to_dev(a), to_dev(b)))
+    e = order_errors(c, ser.star(a, b))
+    assert e.max() < TOL["fp64"], e
+
+
+@pytest.mark.parametrize("n", [1, 2, 15, 16, 17, 63, 64, 65, 100, 130])
+@pytest.mark.parametrize("nt", [0, 1, 5, 15])
+def test_ragged_shapes_fp64(n, nt):
+    a, b = rs(4, n, nt, 0.8), rs(5, n, nt, 0.8)
+    c = to_host(pm.polymat_mul(to_dev(a), to_dev(b)))
+    e = order_errors(c, ser.star(a, b))
+    assert e.max() < TOL["fp64"], e
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("n,nt,r", [(33, 7, 1.0), (70, 31, 0.5), (48, 63, 1.3)])
+def test_precisions_with_auto_rescale(prec, n, nt, r):
+    a, b = rs(6, n, nt, r), rs(7, n, nt, r)
+    c = to_host(pm.polymat_mul(to_dev(a), to_dev(b), precision=prec))
+    e = order_errors(c, ser.star(a, b))
+    assert e.max() < TOL[prec], (prec, e.max(), e)
+
+
+def test_fixed_scale_equals_exact_product():
+    a, b = rs(8, 20, 15, 0.5), rs(9, 20, 15, 0.5)
+    c = to_host(pm.polymat_mul(to_dev(a), to_dev(b), scale=2.0))
+    assert order_errors(c, ser.star(a, b)).max() < TOL["fp64"]
+
+
+def test_output_may_alias_an_input():
+    a, b = rs(10, 24, 7), rs(11, 24, 7)
+    ref = ser.star(a, b)
+    da, db = to_dev(a), to_dev(b)
+    pm.polymat_mul(da, db, C=da)
+    assert order_errors(to_host(da), ref).max() < TOL["fp64"]
+    da, db = to_dev(a), to_dev(b)
+    pm.polymat_mul(da, db, C=db)
+    assert order_errors(to_host(db), ref).max() < TOL["fp64"]
+
+
+def test_bitwise_reproducible():
+    a, b = to_dev(rs(12, 65, 15)), to_dev(rs(13, 65, 15))
+    c1 = to_host(pm.polymat_mul(a, b))
+    c2 = to_host(pm.polymat_mul(a, b))
+    assert np.array_equal(c1, c2)
+
+
+def test_batched_uneven_with_conjugated_operands():
+    shapes = [(9, 7), (20, 3), (33, 15), (5, 0), (64, 31), (17, 12)]
+    items, refs = [], []
+    for i, (n, nt) in enumerate(shapes):
+        a, b = rs(20 + i, n, nt, 0.9), rs(40 + i, n, nt, 0.9)
+        op_a, op_b = i % 2, (i // 2) % 2
+        aa = ser.dagger(a) if op_a else a
+        bb = ser.dagger(b) if op_b else b
+        refs.append(ser.star(aa, bb))
+        items.append(dict(A=to_dev(a), B=to_dev(b), C=torch.empty((nt + 1, n, n), dtype=torch.complex128, device=DEV),
+                          op_a=op_a, op_b=op_b, scale=0.0))
+    pm.polymat_mul_batched(items)
+    for it, ref in zip(items, refs):
+        e = order_errors(to_host(it["C"]), ref)
+        assert e.max() < TOL["fp64"], e
+
+
+def test_batched_matches_single_calls_bitwise():
+    a = [to_dev(rs(60 + i, 40, 15)) for i in range(3)]
+    b = [to_dev(rs(70 + i, 40, 15)) for i in range(3)]
+    single = [to_host(pm.polymat_mul(a[i], b[i])) for i in range(3)]
+    items = [dict(A=a[i], B=b[i], C=torch.empty_like(a[i])) for i in range(3)]
+    pm.polymat_mul_batched(items)
+    for i in range(3):
+        assert np.array_equal(to_host(items[i]["C"]), single[i])
+
+
+def test_paper_scale_four_products_fp64():
+    # one product per direction: N = 225, ntrunc = 31 (L = 64), entries N(0,1) 0.5^k
+    n, nt = 225, 31
+    items, refs = [], []
+    for mu in range(4):
+        a = synth.random_series(synth.rng_for(2, mu, 0), n, nt, 0.5)
+        b = synth.random_series(synth.rng_for(2, mu, 1), n, nt, 0.5)
+        refs.append(ser.star(a, b))
+        items.append(dict(A=to_dev(a), B=to_dev(b), C=torch.empty((nt + 1, n, n), dtype=torch.complex128, device=DEV)))
+    pm.polymat_mul_batched(items, precision="fp64")
+    for it, ref in zip(items, refs):
+        e = order_errors(to_host(it["C"]), ref)
+        assert e.max() < TOL["fp64"], e.max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_paper_scale_growing_series(prec):
+    # N = 225, ntrunc = 63 (L = 128), entries N(0,1) 1.3^k, automatic rescaling
+    n, nt = 225, 63
+    a = synth.random_series(synth.rng_for(3, 0, 0), n, nt, 1.3)
+    b = synth.random_series(synth.rng_for(3, 0, 1), n, nt, 1.3)
+    ref = _cached_star(a, b, key=("c3",))
+    c = to_host(pm.polymat_mul(to_dev(a), to_dev(b), precision=prec))
+    e = order_errors(c, ref)
+    print(f"{prec}: max per-order error {e.max():.3e}")
+    assert e.max() < TOL[prec], e.max()
+
+
+_STAR_CACHE = {}
+
+
+def _cached_star(a, b, key):
+    if key not in _STAR_CACHE:
+        _STAR_CACHE[key] = ser.star(a, b)
+    return _STAR_CACHE[key]
