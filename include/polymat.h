@@ -168,6 +168,26 @@ pm_status polymat_inverse_transform(const void* Ct, void* C, int n, int ntrunc,
 size_t polymat_transform_workspace_size(void);
 
 /*
+ * Phase timing for measurement tools.  While enabled, each kernel launch the
+ * library makes is bracketed by two HIP events recorded on the caller's
+ * stream; polymat_timing_read waits for the recorded events, adds up the
+ * elapsed time and the launch count per phase, and clears the record.
+ * Timing adds two event records per launch and is off by default; it is not
+ * meant to be used under stream capture.
+ *   ms[PM_NUM_PHASES], launches[PM_NUM_PHASES]: host arrays (either may be NULL).
+ */
+enum {
+  PM_PHASE_RESCALE = 0,   /* per-order norms and choice of s */
+  PM_PHASE_FORWARD = 1,   /* Steps 1-2: rescale, pad, forward transform */
+  PM_PHASE_PRODUCT = 2,   /* Step 3: mode-wise complex matrix products */
+  PM_PHASE_INVERSE = 3,   /* Steps 4-5: inverse transform, truncation, unscale */
+  PM_PHASE_OTHER = 4,     /* NSPT element-wise passes */
+  PM_NUM_PHASES = 5
+};
+pm_status polymat_timing_enable(int on);
+pm_status polymat_timing_read(double* ms, int* launches);
+
+/*
  * NSPT Euler-Langevin step of the four-dimensional TEK model (Section 2,
  * eqs. (1)-(3)), for `replicas` independent chains at once.
  *

@@ -15,6 +15,7 @@ PM_OK, PM_ERR_INVALID, PM_ERR_WORKSPACE, PM_ERR_DEVICE, PM_ERR_UNSUPPORTED = ran
 PM_PREC_FP64, PM_PREC_FP32, PM_PREC_BF16X3 = range(3)
 PM_OP_N, PM_OP_C = 0, 1
 PM_MAX_NTRUNC = 63
+PHASES = ("rescale", "forward", "product", "inverse", "other")
 
 
 class PmProblem(ctypes.Structure):
@@ -53,6 +54,8 @@ SIGNATURES = {
     "polymat_forward_transform": (_I, [_VP, _VP, _I, _I, _D, _VP, _SZ, _VP]),
     "polymat_inverse_transform": (_I, [_VP, _VP, _I, _I, _D, _VP, _SZ, _VP]),
     "polymat_transform_workspace_size": (_SZ, []),
+    "polymat_timing_enable": (_I, [_I]),
+    "polymat_timing_read": (_I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
     "nspt_workspace_size": (_SZ, [_I, ctypes.POINTER(NsptParams), _I]),
     "nspt_langevin_step": (_I, [_VP, _VP, _I, ctypes.POINTER(NsptParams), _I, _VP, _SZ, _VP]),
 }

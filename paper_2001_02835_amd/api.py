@@ -164,3 +164,17 @@ def nspt_langevin_step(U: torch.Tensor, eta: torch.Tensor, params: nat.NsptParam
                                       ws.data_ptr(), ws.numel(), _stream_ptr(U.device))
     nat.check(st, "nspt_langevin_step")
     return U
+
+
+def timing_enable(on: bool = True) -> None:
+    """Bracket every library launch with HIP events (for measurement only)."""
+    nat.check(nat.lib().polymat_timing_enable(1 if on else 0), "polymat_timing_enable")
+
+
+def timing_read() -> dict:
+    """{phase: (milliseconds, launches)} since the last read; waits for the events."""
+    n = len(nat.PHASES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int * n)()
+    nat.check(nat.lib().polymat_timing_read(ms, cnt), "polymat_timing_read")
+    return {nat.PHASES[i]: (ms[i], cnt[i]) for i in range(n)}

@@ -60,7 +60,11 @@ struct GemmCfg {
   static_assert((BM * BK) % NT == 0 && (BK * BN) % NT == 0, "tile/thread mismatch");
 };
 
-template <typename T, int WM, int WN, int WGM, int WGN>
+// Uniform (SGPR) copy of a wave-uniform predicate, so the compiler branches on
+// the scalar unit instead of masking lanes.
+__device__ __forceinline__ bool uniform(bool b) { return __builtin_amdgcn_readfirstlane(b ? 1 : 0) != 0; }
+
+template <typename T, int WM, int WN, int WGM, int WGN, bool OPA, bool OPB>
 __global__ __launch_bounds__(kWave * WGM * WGN) void k_cgemm(GemmArgs args) {
   using C = Cx<T>;
   using T2 = typename C::T2;
@@ -86,13 +90,12 @@ __global__ __launch_bounds__(kWave * WGM * WGN) void k_cgemm(GemmArgs args) {
   const int tn = rem - tm * jb.tiles_n;
   const int n = jb.n, L = jb.L;
   const size_t E = static_cast<size_t>(n) * n;
-  const int pa = jb.opA ? (L - p) % L : p;
-  const int pb = jb.opB ? (L - p) % L : p;
+  const int pa = OPA ? (L - p) % L : p;
+  const int pb = OPB ? (L - p) % L : p;
   const T2* __restrict__ Ag = reinterpret_cast<const T2*>(jb.A) + pa * E;
   const T2* __restrict__ Bg = reinterpret_cast<const T2*>(jb.B) + pb * E;
   T2* __restrict__ Cg = reinterpret_cast<T2*>(jb.C) + static_cast<size_t>(p) * E;
   const int row0 = tm * BM, col0 = tn * BN;
-  const bool opA = jb.opA != 0, opB = jb.opB != 0;
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -101,44 +104,58 @@ __global__ __launch_bounds__(kWave * WGM * WGN) void k_cgemm(GemmArgs args) {
   const int wrow0 = wr * 16 * WM, wcol0 = wc * 16 * WN;
   const int li = lane & 15, lk = lane >> 4;
 
-  // ---- global -> register staging
+  // ---- per-thread staging coordinates (fixed over the K loop)
+  // A element (i, k): plain -> Ag[i][k] (coalesced along k); conjugated ->
+  // conj(Ag[k][i]) (coalesced along i).  Same idea for B with (k, j).
+  int a_i[G::LA], a_k[G::LA], b_j[G::LB], b_k[G::LB];
+#pragma unroll
+  for (int u = 0; u < G::LA; ++u) {
+    const int q = tid + NT * u;
+    if (!OPA) { a_k[u] = q % BK; a_i[u] = q / BK; } else { a_i[u] = q % BM; a_k[u] = q / BM; }
+  }
+#pragma unroll
+  for (int u = 0; u < G::LB; ++u) {
+    const int q = tid + NT * u;
+    if (!OPB) { b_j[u] = q % BN; b_k[u] = q / BN; } else { b_k[u] = q % BK; b_j[u] = q / BK; }
+  }
+
   T2 ra[G::LA], rb[G::LB];
+  bool oka[G::LA], okb[G::LB];
+  // Branch-free loads: out-of-range elements read a clamped in-range address;
+  // they are replaced by zero only when written to LDS, so that the loads of
+  // the next chunk stay in flight while the current chunk is multiplied.
   auto load_chunk = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < G::LA; ++u) {
-      const int q = tid + NT * u;
-      int ii, kk;
-      if (!opA) { kk = q % BK; ii = q / BK; } else { ii = q % BM; kk = q / BM; }
-      const int gi = row0 + ii, gk = k0 + kk;
-      T2 v = zero2<T2>();
-      if (gi < n && gk < n) v = opA ? conj2(Ag[static_cast<size_t>(gk) * n + gi]) : Ag[static_cast<size_t>(gi) * n + gk];
-      ra[u] = v;
+      const int gi = row0 + a_i[u], gk = k0 + a_k[u];
+      const bool ok = gi < n && gk < n;
+      const int ci = ok ? gi : 0, ck = ok ? gk : 0;
+      ra[u] = OPA ? Ag[static_cast<size_t>(ck) * n + ci] : Ag[static_cast<size_t>(ci) * n + ck];
+      oka[u] = ok;
     }
 #pragma unroll
     for (int u = 0; u < G::LB; ++u) {
-      const int q = tid + NT * u;
-      int jj, kk;
-      if (!opB) { jj = q % BN; kk = q / BN; } else { kk = q % BK; jj = q / BK; }
-      const int gj = col0 + jj, gk = k0 + kk;
-      T2 v = zero2<T2>();
-      if (gj < n && gk < n) v = opB ? conj2(Bg[static_cast<size_t>(gj) * n + gk]) : Bg[static_cast<size_t>(gk) * n + gj];
-      rb[u] = v;
+      const int gj = col0 + b_j[u], gk = k0 + b_k[u];
+      const bool ok = gj < n && gk < n;
+      const int cj = ok ? gj : 0, ck = ok ? gk : 0;
+      rb[u] = OPB ? Bg[static_cast<size_t>(cj) * n + ck] : Bg[static_cast<size_t>(ck) * n + cj];
+      okb[u] = ok;
     }
   };
   auto store_chunk = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < G::LA; ++u) {
-      const int q = tid + NT * u;
-      int ii, kk;
-      if (!opA) { kk = q % BK; ii = q / BK; } else { ii = q % BM; kk = q / BM; }
-      As[buf][kk][ii] = ra[u];
+      T2 v;
+      v.x = oka[u] ? ra[u].x : T(0);
+      v.y = oka[u] ? (OPA ? -ra[u].y : ra[u].y) : T(0);
+      As[buf][a_k[u]][a_i[u]] = v;
     }
 #pragma unroll
     for (int u = 0; u < G::LB; ++u) {
-      const int q = tid + NT * u;
-      int jj, kk;
-      if (!opB) { jj = q % BN; kk = q / BN; } else { kk = q % BK; jj = q / BK; }
-      Bs[buf][kk][jj] = rb[u];
+      T2 v;
+      v.x = okb[u] ? rb[u].x : T(0);
+      v.y = okb[u] ? (OPB ? -rb[u].y : rb[u].y) : T(0);
+      Bs[buf][b_k[u]][b_j[u]] = v;
     }
   };
 
@@ -151,11 +168,40 @@ __global__ __launch_bounds__(kWave * WGM * WGN) void k_cgemm(GemmArgs args) {
   // wave-uniform activity of each 16x16 block (blocks fully outside the matrix are skipped)
   bool mact[WM], nact[WN];
 #pragma unroll
-  for (int a = 0; a < WM; ++a) mact[a] = row0 + wrow0 + 16 * a < n;
+  for (int a = 0; a < WM; ++a) mact[a] = uniform(row0 + wrow0 + 16 * a < n);
 #pragma unroll
-  for (int b = 0; b < WN; ++b) nact[b] = col0 + wcol0 + 16 * b < n;
+  for (int b = 0; b < WN; ++b) nact[b] = uniform(col0 + wcol0 + 16 * b < n);
+  const bool full = uniform(row0 + BM <= n && col0 + BN <= n);
+
+  auto mma_step = [&](int buf, int s, bool all) {
+    const int kk = 4 * s + lk;
+    T2 fa[WM], fb[WN];
+#pragma unroll
+    for (int a = 0; a < WM; ++a) fa[a] = As[buf][kk][wrow0 + 16 * a + li];
+#pragma unroll
+    for (int b = 0; b < WN; ++b) fb[b] = Bs[buf][kk][wcol0 + 16 * b + li];
+#pragma unroll
+    for (int a = 0; a < WM; ++a) {
+      const T nai = -fa[a].y;
+#pragma unroll
+      for (int b = 0; b < WN; ++b) {
+        if (all || (mact[a] && nact[b])) {
+          cr[a][b] = C::mfma(fa[a].x, fb[b].x, cr[a][b]);
+          ci[a][b] = C::mfma(fa[a].x, fb[b].y, ci[a][b]);
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < WN; ++b) {
+        if (all || (mact[a] && nact[b])) {
+          cr[a][b] = C::mfma(nai, fb[b].y, cr[a][b]);
+          ci[a][b] = C::mfma(fa[a].y, fb[b].x, ci[a][b]);
+        }
+      }
+    }
+  };
 
   const int nchunks = (n + BK - 1) / BK;
+  const int nfull = n / BK;            // chunks with every k-step inside the matrix
   load_chunk(0);
   store_chunk(0);
   __syncthreads();
@@ -163,29 +209,13 @@ __global__ __launch_bounds__(kWave * WGM * WGN) void k_cgemm(GemmArgs args) {
     const int buf = c & 1;
     const int k0 = c * BK;
     if (c + 1 < nchunks) load_chunk(k0 + BK);
+    if (full && c < nfull) {
 #pragma unroll
-    for (int s = 0; s < BK / 4; ++s) {
-      if (k0 + 4 * s < n) {
-        const int kk = 4 * s + lk;
-        T2 fa[WM], fb[WN];
+      for (int s = 0; s < BK / 4; ++s) mma_step(buf, s, true);
+    } else {
 #pragma unroll
-        for (int a = 0; a < WM; ++a) fa[a] = As[buf][kk][wrow0 + 16 * a + li];
-#pragma unroll
-        for (int b = 0; b < WN; ++b) fb[b] = Bs[buf][kk][wcol0 + 16 * b + li];
-#pragma unroll
-        for (int a = 0; a < WM; ++a) {
-          const T nai = -fa[a].y;
-#pragma unroll
-          for (int b = 0; b < WN; ++b) {
-            if (mact[a] && nact[b]) {
-              cr[a][b] = C::mfma(fa[a].x, fb[b].x, cr[a][b]);
-              ci[a][b] = C::mfma(fa[a].x, fb[b].y, ci[a][b]);
-              cr[a][b] = C::mfma(nai, fb[b].y, cr[a][b]);
-              ci[a][b] = C::mfma(fa[a].y, fb[b].x, ci[a][b]);
-            }
-          }
-        }
-      }
+      for (int s = 0; s < BK / 4; ++s)
+        if (k0 + 4 * s < n) mma_step(buf, s, false);
     }
     if (c + 1 < nchunks) store_chunk(buf ^ 1);
     __syncthreads();
@@ -217,21 +247,26 @@ constexpr int kWM = 2, kWN = 2, kWGM = 2, kWGN = 2;
 }  // namespace
 
 int gemm_tile(FourierType t) {
-  (void)t;
-  return 16 * kWM * kWGM;
+  return t == kBF16Split ? gemm_tile_bf16() : 16 * kWM * kWGM;
+}
+
+template <typename T>
+hipError_t launch_typed(const GemmArgs& a, hipStream_t s) {
+  // all jobs of one launch share their operand forms (the host groups them)
+  const int oa = a.jobs[0].opA, ob = a.jobs[0].opB;
+  constexpr int nt = kWave * kWGM * kWGN;
+  if (!oa && !ob) k_cgemm<T, kWM, kWN, kWGM, kWGN, false, false><<<a.total_tiles, nt, 0, s>>>(a);
+  else if (!oa && ob) k_cgemm<T, kWM, kWN, kWGM, kWGN, false, true><<<a.total_tiles, nt, 0, s>>>(a);
+  else if (oa && !ob) k_cgemm<T, kWM, kWN, kWGM, kWGN, true, false><<<a.total_tiles, nt, 0, s>>>(a);
+  else k_cgemm<T, kWM, kWN, kWGM, kWGN, true, true><<<a.total_tiles, nt, 0, s>>>(a);
+  return hipGetLastError();
 }
 
 hipError_t launch_gemm(const GemmArgs& a, FourierType t, hipStream_t s) {
   if (a.njobs <= 0 || a.total_tiles <= 0) return hipSuccess;
-  constexpr int nt = kWave * kWGM * kWGN;
-  if (t == kF64) {
-    k_cgemm<double, kWM, kWN, kWGM, kWGN><<<a.total_tiles, nt, 0, s>>>(a);
-  } else if (t == kF32) {
-    k_cgemm<float, kWM, kWN, kWGM, kWGN><<<a.total_tiles, nt, 0, s>>>(a);
-  } else {
-    return hipErrorInvalidValue;   // the split-BF16 products live in pm_gemm_bf16.hip
-  }
-  return hipGetLastError();
+  if (t == kF64) return launch_typed<double>(a, s);
+  if (t == kF32) return launch_typed<float>(a, s);
+  return launch_gemm_bf16(a, s);
 }
 
 }  // namespace pm

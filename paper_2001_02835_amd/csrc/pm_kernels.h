@@ -18,8 +18,8 @@ struct FwdJob {
   const ScaleRec* rec;     // s^k table
   int E;                   // n * n
   int nord;                // ntrunc + 1
-  int n;                   // matrix size (for the BF16 blocked layout)
-  int role;                // BF16 only: 0 = left factor, 1 = right factor
+  int n;                   // matrix size (row length of the BF16 planes)
+  int pad_;
 };
 
 // Inverse transform job: C^(k) = s^-k (1/L) sum_p Ct^(p) w^{-kp}, k < nord.
@@ -91,6 +91,8 @@ struct GemmArgs { GemmJob jobs[kMaxGemmJobs]; int njobs; int total_tiles; };
 // Tile edge of the products for a precision (rows and columns per tile).
 int gemm_tile(FourierType t);
 hipError_t launch_gemm(const GemmArgs& a, FourierType t, hipStream_t s);
+int gemm_tile_bf16();
+hipError_t launch_gemm_bf16(const GemmArgs& a, hipStream_t s);
 
 // Leading dimension (elements) of one BF16 plane row for matrix size n.
 __host__ __device__ inline int bf16_ld(int n) { return (n + 7) / 8 * 8; }

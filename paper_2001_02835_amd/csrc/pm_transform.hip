@@ -49,11 +49,10 @@ __device__ __forceinline__ void split_bf16(double x, uint16_t& hi, uint16_t& lo)
 }
 
 // BF16 split layout of one mode: four planes (re_hi, re_lo, im_hi, im_lo),
-// each [n / 8 blocks of k][rows][8], where k is the contracted index: for the
-// left factor rows = i and k = j; for the right factor rows = j and k = i.
-// A lane of the product kernel then reads 8 consecutive k of one row with a
-// single 16-byte load.  Plane size: ceil(n/8) * 8 * n elements (zero padded
-// in k up to a multiple of 8).
+// each row-major [n][ld] with ld = n rounded up to a multiple of 8, so that a
+// lane of the product kernel can fetch 8 consecutive entries of a row with a
+// single 16-byte load.  The padding columns are never written (the product
+// kernel masks them).
 __device__ __forceinline__ size_t bf16_plane_elems(int n) { return static_cast<size_t>(bf16_ld(n)) * n; }
 
 template <FourierType FT>
@@ -66,11 +65,9 @@ __device__ __forceinline__ void store_mode(const FwdJob& jb, int p, int e, doubl
   } else {
     const int n = jb.n;
     const int i = e / n, j = e - (e / n) * n;
-    const int row = jb.role == 0 ? i : j;
-    const int kk = jb.role == 0 ? j : i;
     const size_t plane = bf16_plane_elems(n);
     uint16_t* base = reinterpret_cast<uint16_t*>(jb.dst) + static_cast<size_t>(p) * 4 * plane;
-    const size_t off = (static_cast<size_t>(kk >> 3) * n + row) * 8 + (kk & 7);
+    const size_t off = static_cast<size_t>(i) * bf16_ld(n) + j;
     uint16_t rh, rl, ih, il;
     split_bf16(v.x, rh, rl);
     split_bf16(v.y, ih, il);
@@ -240,13 +237,15 @@ __global__ __launch_bounds__(256) void k_norms(NormArgs args) {
 // c_m = sum_j a_j b_{m-j} (m <= 2 ntrunc, the orders of the full product,
 // including those the truncation discards), minimise the spread
 //   f(t) = max_m (log c_m + m t) - min_{k <= ntrunc} (log c_k + k t)
-// over the nonzero c.  f is convex and piecewise linear; 256 threads
-// evaluate it on a grid, three refinement rounds.
-__global__ __launch_bounds__(256) void k_scale(ScaleArgs args) {
-  __shared__ double na[kMaxL / 2], nb[kMaxL / 2], lc[kMaxL];
-  __shared__ double fval[256];
-  __shared__ int fidx[256];
-  __shared__ double t_best;
+// over the nonzero c.  f is convex and piecewise linear.  One wavefront
+// evaluates it on a 64-point grid; three refinement rounds shrink the grid
+// spacing by 32 each.
+constexpr double kAbsent = 1e300;
+
+__global__ __launch_bounds__(64) void k_scale(ScaleArgs args) {
+  __shared__ double na[kMaxL / 2], nb[kMaxL / 2];
+  __shared__ double lmax[kMaxL], lmin[kMaxL / 2];
+  __shared__ double fval[64];
   const ScaleJob& jb = args.jobs[blockIdx.x];
   const int nord = jb.nord;
   const int tid = threadIdx.x;
@@ -265,57 +264,47 @@ __global__ __launch_bounds__(256) void k_scale(ScaleArgs args) {
     }
     __syncthreads();
     const int nm = 2 * nord - 1;
-    if (tid < nm) {
+    for (int m = tid; m < nm; m += 64) {
       double c = 0.0;
-      const int j0 = max(0, tid - (nord - 1)), j1 = min(tid, nord - 1);
-      for (int j = j0; j <= j1; ++j) c = fma(na[j], nb[tid - j], c);
-      lc[tid] = (c > 0.0 && isfinite(c)) ? log(c) : -INFINITY;
+      const int j0 = max(0, m - (nord - 1)), j1 = min(m, nord - 1);
+      for (int j = j0; j <= j1; ++j) c = fma(na[j], nb[m - j], c);
+      const bool ok = c > 0.0 && isfinite(c);
+      const double lc = ok ? log(c) : 0.0;
+      lmax[m] = ok ? lc : -kAbsent;
+      if (m < nord) lmin[m] = ok ? lc : kAbsent;
     }
     __syncthreads();
     bool any = false;
-    for (int k = 0; k < nord; ++k) any |= (lc[k] > -INFINITY);
+    for (int k = 0; k < nord; ++k) any |= lmin[k] < kAbsent;
     if (any) {
-      double span = 300.0 / (2.0 * (nord - 1));
-      double lo = -span, hi = span;
+      double lo = -300.0 / (2.0 * (nord - 1)), hi = -lo;
       for (int round = 0; round < 3; ++round) {
-        const double tt = lo + (hi - lo) * tid / 255.0;
-        double mx = -INFINITY, mn = INFINITY;
-        for (int m = 0; m < nm; ++m) {
-          double v = lc[m] + m * tt;
-          if (lc[m] > -INFINITY) mx = fmax(mx, v);
-          if (m < nord && lc[m] > -INFINITY) mn = fmin(mn, v);
+        const double step = (hi - lo) / 63.0;
+        const double tt = lo + step * tid;
+        double mx = -kAbsent, mn = kAbsent;
+        for (int m = 0; m < nord; ++m) {
+          mx = fmax(mx, fma(static_cast<double>(m), tt, lmax[m]));
+          mn = fmin(mn, fma(static_cast<double>(m), tt, lmin[m]));
         }
+        for (int m = nord; m < nm; ++m) mx = fmax(mx, fma(static_cast<double>(m), tt, lmax[m]));
         fval[tid] = mx - mn;
-        fidx[tid] = tid;
         __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-          if (tid < w) {
-            double f2 = fval[tid + w];
-            int i2 = fidx[tid + w];
-            if (f2 < fval[tid] || (f2 == fval[tid] && i2 < fidx[tid])) {
-              fval[tid] = f2;
-              fidx[tid] = i2;
-            }
-          }
-          __syncthreads();
-        }
-        const double step = (hi - lo) / 255.0;
-        const double tb = lo + step * fidx[0];
+        int best = 0;
+        double fb = fval[0];
+        for (int i = 1; i < 64; ++i)
+          if (fval[i] < fb) { fb = fval[i]; best = i; }
         __syncthreads();
+        const double tb = lo + step * best;
         lo = tb - step;
         hi = tb + step;
-        if (tid == 0) t_best = tb;
+        t = tb;
       }
-      __syncthreads();
-      t = t_best;
     }
   }
   ScaleRec* rec = jb.rec;
   if (tid == 0) rec->s = exp(t);
-  if (tid < kMaxL / 2) {
-    rec->spow[tid] = exp(t * tid);
-    rec->sinv[tid] = exp(-t * tid) / jb.L;
-  }
+  rec->spow[tid] = exp(t * tid);
+  rec->sinv[tid] = exp(-t * tid) / jb.L;
 }
 
 template <FourierType FT>
@@ -376,7 +365,7 @@ hipError_t launch_norms(const NormArgs& a, int max_nord, hipStream_t s) {
 
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s) {
   if (a.njobs <= 0) return hipSuccess;
-  k_scale<<<a.njobs, 256, 0, s>>>(a);
+  k_scale<<<a.njobs, 64, 0, s>>>(a);
   return hipGetLastError();
 }
 

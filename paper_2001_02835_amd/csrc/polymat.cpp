@@ -12,7 +12,9 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <atomic>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "pm_common.h"
@@ -96,6 +98,39 @@ pm_status check_problem_shape(const void* A, const void* B, const void* C, int n
 
 pm_status from_hip(hipError_t e) { return e == hipSuccess ? PM_OK : PM_ERR_DEVICE; }
 
+// ------------------------------------------------------------ phase timing
+
+struct TimingRec { int phase; hipEvent_t a, b; };
+std::atomic<bool> g_timing{false};
+std::mutex g_tmu;
+std::vector<TimingRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t pooled_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Run `launch` (a callable returning hipError_t), bracketed by events when
+// timing is enabled.
+template <typename F>
+hipError_t timed(int phase, hipStream_t st, F&& launch) {
+  if (!g_timing.load(std::memory_order_relaxed)) return launch();
+  std::lock_guard<std::mutex> lk(g_tmu);
+  hipEvent_t a = pooled_event(), b = pooled_event();
+  if (a) (void)hipEventRecord(a, st);
+  hipError_t e = launch();
+  if (b) (void)hipEventRecord(b, st);
+  if (a && b) g_recs.push_back(TimingRec{phase, a, b});
+  return e;
+}
+
 // Enqueue the whole FFT-CONV pipeline for a list of validated problems whose
 // workspace regions are given.
 struct Planned {
@@ -114,7 +149,7 @@ pm_status enqueue_products(const std::vector<Planned>& items, int prec, hipStrea
     int max_nord = 0;
     auto flush = [&]() -> pm_status {
       if (na.njobs == 0) return PM_OK;
-      pm_status s = from_hip(launch_norms(na, max_nord, st));
+      pm_status s = from_hip(timed(PM_PHASE_RESCALE, st, [&] { return launch_norms(na, max_nord, st); }));
       na.njobs = 0;
       max_nord = 0;
       return s;
@@ -141,7 +176,7 @@ pm_status enqueue_products(const std::vector<Planned>& items, int prec, hipStrea
     ScaleArgs sa{};
     for (const Planned& it : items) {
       if (sa.njobs == kMaxTransformJobs) {
-        pm_status s = from_hip(launch_scale(sa, st));
+        pm_status s = from_hip(timed(PM_PHASE_RESCALE, st, [&] { return launch_scale(sa, st); }));
         if (s) return s;
         sa.njobs = 0;
       }
@@ -153,7 +188,7 @@ pm_status enqueue_products(const std::vector<Planned>& items, int prec, hipStrea
       j.L = it.L;
       j.fixed_s = it.pr.scale;
     }
-    pm_status s = from_hip(launch_scale(sa, st));
+    pm_status s = from_hip(timed(PM_PHASE_RESCALE, st, [&] { return launch_scale(sa, st); }));
     if (s) return s;
   }
   // 3. forward transforms, one launch per transform length (and per 64 jobs)
@@ -164,7 +199,7 @@ pm_status enqueue_products(const std::vector<Planned>& items, int prec, hipStrea
     int maxE = 0;
     auto flush = [&]() -> pm_status {
       if (fa.njobs == 0) return PM_OK;
-      pm_status s = from_hip(launch_forward(fa, kv.first, maxE, ft, st));
+      pm_status s = from_hip(timed(PM_PHASE_FORWARD, st, [&] { return launch_forward(fa, kv.first, maxE, ft, st); }));
       fa.njobs = 0;
       maxE = 0;
       return s;
@@ -179,29 +214,25 @@ pm_status enqueue_products(const std::vector<Planned>& items, int prec, hipStrea
         j.E = it->pr.n * it->pr.n;
         j.nord = it->pr.ntrunc + 1;
         j.n = it->pr.n;
-        // BF16 layout role: the factor's contracted index is its column for
-        // the left factor and its row for the right factor; a conjugated
-        // operand swaps the two.
-        const int op = side == 0 ? it->pr.op_a : it->pr.op_b;
-        j.role = (side ^ op) & 1;
         maxE = std::max(maxE, j.E);
       }
     }
     pm_status s = flush();
     if (s) return s;
   }
-  // 4. mode-wise products
-  {
+  // 4. mode-wise products, one launch per operand form (and per 48 jobs)
+  for (int form = 0; form < 4; ++form) {
     GemmArgs ga{};
     const int tile = gemm_tile(ft);
     auto flush = [&]() -> pm_status {
       if (ga.njobs == 0) return PM_OK;
-      pm_status s = from_hip(launch_gemm(ga, ft, st));
+      pm_status s = from_hip(timed(PM_PHASE_PRODUCT, st, [&] { return launch_gemm(ga, ft, st); }));
       ga.njobs = 0;
       ga.total_tiles = 0;
       return s;
     };
     for (const Planned& it : items) {
+      if (it.pr.op_a * 2 + it.pr.op_b != form) continue;
       if (ga.njobs == kMaxGemmJobs) { pm_status s = flush(); if (s) return s; }
       GemmJob& j = ga.jobs[ga.njobs++];
       j.A = it.ws + it.lay.At;
@@ -225,7 +256,7 @@ pm_status enqueue_products(const std::vector<Planned>& items, int prec, hipStrea
     int maxE = 0;
     auto flush = [&]() -> pm_status {
       if (ia.njobs == 0) return PM_OK;
-      pm_status s = from_hip(launch_inverse(ia, kv.first, maxE, ft, st));
+      pm_status s = from_hip(timed(PM_PHASE_INVERSE, st, [&] { return launch_inverse(ia, kv.first, maxE, ft, st); }));
       ia.njobs = 0;
       maxE = 0;
       return s;
@@ -285,6 +316,43 @@ pm_status plan_batch(const pm_problem* problems, int count, int prec, char* ws, 
 extern "C" {
 
 int polymat_abi_version(void) { return 1; }
+
+pm_status polymat_timing_enable(int on) {
+  g_timing.store(on != 0);
+  return PM_OK;
+}
+
+pm_status polymat_timing_read(double* ms, int* launches) {
+  std::vector<TimingRec> recs;
+  {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    recs.swap(g_recs);
+  }
+  double acc[PM_NUM_PHASES] = {0};
+  int cnt[PM_NUM_PHASES] = {0};
+  pm_status st = PM_OK;
+  for (const TimingRec& r : recs) {
+    float t = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) {
+      st = PM_ERR_DEVICE;
+    } else if (r.phase >= 0 && r.phase < PM_NUM_PHASES) {
+      acc[r.phase] += t;
+      cnt[r.phase] += 1;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (const TimingRec& r : recs) {
+      g_pool.push_back(r.a);
+      g_pool.push_back(r.b);
+    }
+  }
+  for (int i = 0; i < PM_NUM_PHASES; ++i) {
+    if (ms) ms[i] = acc[i];
+    if (launches) launches[i] = cnt[i];
+  }
+  return st;
+}
 
 const char* polymat_strerror(pm_status status) {
   switch (status) {
@@ -384,7 +452,6 @@ pm_status polymat_forward_transform(const void* A, void* At, int n, int ntrunc, 
   fa.jobs[0].E = n * n;
   fa.jobs[0].nord = ntrunc + 1;
   fa.jobs[0].n = n;
-  fa.jobs[0].role = 0;
   return from_hip(launch_forward(fa, L, n * n, kF64, st));
 }
 
