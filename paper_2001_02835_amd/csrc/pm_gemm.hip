@@ -17,6 +17,8 @@
 #include "pm_common.h"
 #include "pm_kernels.h"
 
+#include <cstdlib>
+
 namespace pm {
 
 namespace {
@@ -64,7 +66,12 @@ struct GemmCfg {
 // the scalar unit instead of masking lanes.
 __device__ __forceinline__ bool uniform(bool b) { return __builtin_amdgcn_readfirstlane(b ? 1 : 0) != 0; }
 
-template <typename T, int WM, int WN, int WGM, int WGN, bool OPA, bool OPB>
+// G3 selects the three-product form of the complex multiply-accumulate
+// (Gauss): P1 += Xr Yr, P2 += Xi Yi, P3 += (Xr + Xi)(Yr + Yi), then
+// Re = P1 - P2, Im = P3 - P1 - P2.  It issues 3 MFMAs per k-step and block
+// instead of 4; the sums Xr + Xi and Yr + Yi are formed in registers from the
+// staged fragments, so memory traffic is unchanged.
+template <typename T, int WM, int WN, int WGM, int WGN, bool OPA, bool OPB, bool G3>
 __global__ __launch_bounds__(kWave * WGM * WGN) void k_cgemm(GemmArgs args) {
   using C = Cx<T>;
   using T2 = typename C::T2;
@@ -159,49 +166,74 @@ __global__ __launch_bounds__(kWave * WGM * WGN) void k_cgemm(GemmArgs args) {
     }
   };
 
-  Acc cr[WM][WN], ci[WM][WN];
+  // 4-product form: cr, ci.  3-product form: cr = P1, ci = P2, c3 = P3.
+  Acc cr[WM][WN], ci[WM][WN], c3[G3 ? WM : 1][G3 ? WN : 1];
 #pragma unroll
   for (int a = 0; a < WM; ++a)
 #pragma unroll
     for (int b = 0; b < WN; ++b) { cr[a][b] = Acc{0, 0, 0, 0}; ci[a][b] = Acc{0, 0, 0, 0}; }
+  if constexpr (G3) {
+#pragma unroll
+    for (int a = 0; a < WM; ++a)
+#pragma unroll
+      for (int b = 0; b < WN; ++b) c3[a][b] = Acc{0, 0, 0, 0};
+  }
 
   // wave-uniform activity of each 16x16 block (blocks fully outside the matrix are skipped)
-  bool mact[WM], nact[WN];
+  bool act[WM][WN];
 #pragma unroll
-  for (int a = 0; a < WM; ++a) mact[a] = uniform(row0 + wrow0 + 16 * a < n);
+  for (int a = 0; a < WM; ++a)
 #pragma unroll
-  for (int b = 0; b < WN; ++b) nact[b] = uniform(col0 + wcol0 + 16 * b < n);
-  const bool full = uniform(row0 + BM <= n && col0 + BN <= n);
+    for (int b = 0; b < WN; ++b)
+      act[a][b] = uniform(row0 + wrow0 + 16 * a < n && col0 + wcol0 + 16 * b < n);
 
-  auto mma_step = [&](int buf, int s, bool all) {
+  auto mma_step = [&](int buf, int s) {
     const int kk = 4 * s + lk;
     T2 fa[WM], fb[WN];
 #pragma unroll
     for (int a = 0; a < WM; ++a) fa[a] = As[buf][kk][wrow0 + 16 * a + li];
 #pragma unroll
     for (int b = 0; b < WN; ++b) fb[b] = Bs[buf][kk][wcol0 + 16 * b + li];
+    if constexpr (G3) {
+      T sa[WM], sb[WN];
 #pragma unroll
-    for (int a = 0; a < WM; ++a) {
-      const T nai = -fa[a].y;
+      for (int a = 0; a < WM; ++a) sa[a] = fa[a].x + fa[a].y;
 #pragma unroll
-      for (int b = 0; b < WN; ++b) {
-        if (all || (mact[a] && nact[b])) {
-          cr[a][b] = C::mfma(fa[a].x, fb[b].x, cr[a][b]);
-          ci[a][b] = C::mfma(fa[a].x, fb[b].y, ci[a][b]);
+      for (int b = 0; b < WN; ++b) sb[b] = fb[b].x + fb[b].y;
+#pragma unroll
+      for (int a = 0; a < WM; ++a) {
+#pragma unroll
+        for (int b = 0; b < WN; ++b) {
+          if (act[a][b]) {
+            cr[a][b] = C::mfma(fa[a].x, fb[b].x, cr[a][b]);
+            ci[a][b] = C::mfma(fa[a].y, fb[b].y, ci[a][b]);
+            c3[a][b] = C::mfma(sa[a], sb[b], c3[a][b]);
+          }
         }
       }
+    } else {
 #pragma unroll
-      for (int b = 0; b < WN; ++b) {
-        if (all || (mact[a] && nact[b])) {
-          cr[a][b] = C::mfma(nai, fb[b].y, cr[a][b]);
-          ci[a][b] = C::mfma(fa[a].y, fb[b].x, ci[a][b]);
+      for (int a = 0; a < WM; ++a) {
+        const T nai = -fa[a].y;
+#pragma unroll
+        for (int b = 0; b < WN; ++b) {
+          if (act[a][b]) {
+            cr[a][b] = C::mfma(fa[a].x, fb[b].x, cr[a][b]);
+            ci[a][b] = C::mfma(fa[a].x, fb[b].y, ci[a][b]);
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < WN; ++b) {
+          if (act[a][b]) {
+            cr[a][b] = C::mfma(nai, fb[b].y, cr[a][b]);
+            ci[a][b] = C::mfma(fa[a].y, fb[b].x, ci[a][b]);
+          }
         }
       }
     }
   };
 
   const int nchunks = (n + BK - 1) / BK;
-  const int nfull = n / BK;            // chunks with every k-step inside the matrix
   load_chunk(0);
   store_chunk(0);
   __syncthreads();
@@ -209,14 +241,9 @@ __global__ __launch_bounds__(kWave * WGM * WGN) void k_cgemm(GemmArgs args) {
     const int buf = c & 1;
     const int k0 = c * BK;
     if (c + 1 < nchunks) load_chunk(k0 + BK);
-    if (full && c < nfull) {
 #pragma unroll
-      for (int s = 0; s < BK / 4; ++s) mma_step(buf, s, true);
-    } else {
-#pragma unroll
-      for (int s = 0; s < BK / 4; ++s)
-        if (k0 + 4 * s < n) mma_step(buf, s, false);
-    }
+    for (int s = 0; s < BK / 4; ++s)
+      if (k0 + 4 * s < n) mma_step(buf, s);
     if (c + 1 < nchunks) store_chunk(buf ^ 1);
     __syncthreads();
   }
@@ -232,8 +259,13 @@ __global__ __launch_bounds__(kWave * WGM * WGN) void k_cgemm(GemmArgs args) {
         const int gi = row0 + wrow0 + 16 * a + C::out_row(lane, v);
         if (gi < n && gj < n) {
           T2 o;
-          o.x = cr[a][b][v];
-          o.y = ci[a][b][v];
+          if constexpr (G3) {
+            o.x = cr[a][b][v] - ci[a][b][v];
+            o.y = c3[a][b][v] - cr[a][b][v] - ci[a][b][v];
+          } else {
+            o.x = cr[a][b][v];
+            o.y = ci[a][b][v];
+          }
           Cg[static_cast<size_t>(gi) * n + gj] = o;
         }
       }
@@ -242,6 +274,12 @@ __global__ __launch_bounds__(kWave * WGM * WGN) void k_cgemm(GemmArgs args) {
 }
 
 // Tile shapes: 64 x 64 tiles with four wavefronts of 2 x 2 blocks.
+// Three-product complex form on by default; POLYMAT_GEMM_4M=1 in the
+// environment selects the four-product form (read once per process).
+const bool g_gemm_g3 = [] {
+  const char* e = getenv("POLYMAT_GEMM_4M");
+  return !(e && e[0] == '1');
+}();
 constexpr int kWM = 2, kWN = 2, kWGM = 2, kWGN = 2;
 
 }  // namespace
@@ -250,22 +288,22 @@ int gemm_tile(FourierType t) {
   return t == kBF16Split ? gemm_tile_bf16() : 16 * kWM * kWGM;
 }
 
-template <typename T>
+template <typename T, bool G3>
 hipError_t launch_typed(const GemmArgs& a, hipStream_t s) {
   // all jobs of one launch share their operand forms (the host groups them)
   const int oa = a.jobs[0].opA, ob = a.jobs[0].opB;
   constexpr int nt = kWave * kWGM * kWGN;
-  if (!oa && !ob) k_cgemm<T, kWM, kWN, kWGM, kWGN, false, false><<<a.total_tiles, nt, 0, s>>>(a);
-  else if (!oa && ob) k_cgemm<T, kWM, kWN, kWGM, kWGN, false, true><<<a.total_tiles, nt, 0, s>>>(a);
-  else if (oa && !ob) k_cgemm<T, kWM, kWN, kWGM, kWGN, true, false><<<a.total_tiles, nt, 0, s>>>(a);
-  else k_cgemm<T, kWM, kWN, kWGM, kWGN, true, true><<<a.total_tiles, nt, 0, s>>>(a);
+  if (!oa && !ob) k_cgemm<T, kWM, kWN, kWGM, kWGN, false, false, G3><<<a.total_tiles, nt, 0, s>>>(a);
+  else if (!oa && ob) k_cgemm<T, kWM, kWN, kWGM, kWGN, false, true, G3><<<a.total_tiles, nt, 0, s>>>(a);
+  else if (oa && !ob) k_cgemm<T, kWM, kWN, kWGM, kWGN, true, false, G3><<<a.total_tiles, nt, 0, s>>>(a);
+  else k_cgemm<T, kWM, kWN, kWGM, kWGN, true, true, G3><<<a.total_tiles, nt, 0, s>>>(a);
   return hipGetLastError();
 }
 
 hipError_t launch_gemm(const GemmArgs& a, FourierType t, hipStream_t s) {
   if (a.njobs <= 0 || a.total_tiles <= 0) return hipSuccess;
-  if (t == kF64) return launch_typed<double>(a, s);
-  if (t == kF32) return launch_typed<float>(a, s);
+  if (t == kF64) return g_gemm_g3 ? launch_typed<double, true>(a, s) : launch_typed<double, false>(a, s);
+  if (t == kF32) return g_gemm_g3 ? launch_typed<float, true>(a, s) : launch_typed<float, false>(a, s);
   return launch_gemm_bf16(a, s);
 }
 

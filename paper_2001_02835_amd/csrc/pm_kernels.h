@@ -55,12 +55,14 @@ struct NormJob {
 struct NormArgs { NormJob jobs[kMaxTransformJobs]; int njobs; };
 
 struct ScaleJob {
-  const double* partA;     // [nord][kNormChunks] or null when s is fixed
-  const double* partB;
+  const double* partA;     // [nser][nord][kNormChunks] or null when s is fixed
+  const double* partB;     // (norms of nser stacked series are combined)
   ScaleRec* rec;
   int nord;
   int L;
   double fixed_s;          // > 0: use it; 0: choose from the norms
+  int nser;
+  int pad_;
 };
 struct ScaleArgs { ScaleJob jobs[kMaxTransformJobs]; int njobs; };
 

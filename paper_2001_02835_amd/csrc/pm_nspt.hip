@@ -1,33 +1,511 @@
-// NSPT Euler-Langevin step of the TEK model (validation only so far).
+// Host orchestration of one NSPT Euler-Langevin step of the TEK model
+// (eqs. (1)-(3)) for R replicas at once, on the FFT-CONV building blocks.
+//
+// One rescale factor s is chosen per call from the per-order norms of all
+// link series; every series of the step then lives in the rescaled variable
+// (order k multiplied by s^k), which keeps all Fourier-space products
+// consistent with each other.  With U~ the transforms of the old links:
+//
+//  staples (42 products per replica, 24 re-truncations)
+//    Q_mn = U_m * U_n           (m != n)      R_mn = U_m * U_n^+   (m < n)
+//    W_mn = U_m^+ * U_n         (m < n)
+//    P_mn = Q_mn * Q_nm^+       (m < n)       T_mn = R_mn * W_mn   (all m != n;
+//                                              R_mn = R_nm^+, W_mn = W_nm^+ for m > n)
+//    The force needs D_m = S_m - S_m^+ only, and the plaquette terms of S_m and
+//    S_n are conjugate to each other, so D_m = M_m - M_m^+ with
+//    M_m = sum_{n>m} z_mn P_mn - sum_{n<m} z_nm P_nm + sum_{n!=m} z_mn^* T_mn,
+//    formed in Fourier space and transformed back once per direction.
+//  drift and noise
+//    Y_m = i X_m = -eps (D - Tr D / N) + i sqrt(2 eps) eta_m g,  Y^(0) = 0
+//  exponential, Paterson-Stockmeyer with block b ~ sqrt(ntrunc + 1)
+//    Y^2..Y^b by products; E = sum_q (Y^b)^q B_q(Y), B_q = sum_{i<b} Y^i / (qb + i)!
+//    by Horner in Y^b; B_q is added inside the re-truncation of each link.
+//  link update
+//    U_m <- E_m * U_m, order 0 left as it is (E^(0) = 1 exactly).
 #include <cmath>
+#include <vector>
 
+#include "pm_common.h"
+#include "pm_kernels.h"
 #include "pm_nspt.h"
+#include "pm_nspt_kernels.h"
 
 namespace pm {
 
 namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
 bool valid_params(int replicas, const nspt_params* p, int prec) {
-  if (!p || replicas < 1) return false;
+  if (!p || replicas < 1 || replicas > 1024) return false;
   if (prec != PM_PREC_FP64 && prec != PM_PREC_FP32 && prec != PM_PREC_BF16X3) return false;
-  if (p->L < 1 || p->L % 2 == 0 || p->n != p->L * p->L) return false;
+  if (p->L < 1 || p->L % 2 == 0 || p->L > 64 || p->n != p->L * p->L) return false;
   if (p->ntrunc < 0 || p->ntrunc > PM_MAX_NTRUNC) return false;
   if (!std::isfinite(p->eps) || p->eps <= 0.0) return false;
   return true;
 }
+
+int tlength(int ntrunc) {
+  int L = 4;
+  while (L < 2 * (ntrunc + 1)) L *= 2;
+  return L;
+}
+
+int ps_block(int ntrunc) {
+  int b = 1;
+  while (b * b < ntrunc + 1) ++b;
+  return b;
+}
+
+FourierType in_type(int prec) { return prec == PM_PREC_FP64 ? kF64 : (prec == PM_PREC_FP32 ? kF32 : kBF16Split); }
+FourierType out_type(int prec) { return prec == PM_PREC_FP64 ? kF64 : kF32; }
+
+// Workspace layout (per call, all replicas).
+struct Layout {
+  int n, E, nord, L, R, b;
+  size_t fin, fout, tser;        // bytes: Fourier (product input), Fourier (product output), time series
+  size_t rec, unit, part, trc;   // small tables
+  size_t Ut, G, Xt, M, Ypt, Ypf, Z;
+  size_t total;
+};
+
+Layout layout(int R, const nspt_params* p, int prec) {
+  Layout l{};
+  l.n = p->n;
+  l.E = p->n * p->n;
+  l.nord = p->ntrunc + 1;
+  l.L = tlength(p->ntrunc);
+  l.R = R;
+  l.b = ps_block(p->ntrunc);
+  const size_t E = static_cast<size_t>(l.E);
+  l.fin = align_up(prec == PM_PREC_FP64 ? E * l.L * 16
+                   : prec == PM_PREC_FP32 ? E * l.L * 8
+                                          : static_cast<size_t>(bf16_ld(l.n)) * l.n * 8 * l.L);
+  l.fout = align_up(E * l.L * (prec == PM_PREC_FP64 ? 16 : 8));
+  l.tser = align_up(E * l.nord * 16);
+  size_t off = 0;
+  l.rec = off;  off += align_up(sizeof(ScaleRec));
+  l.unit = off; off += align_up(sizeof(ScaleRec));
+  l.part = off; off += align_up(static_cast<size_t>(4) * R * l.nord * kNormChunks * sizeof(double));
+  l.trc = off;  off += align_up(static_cast<size_t>(4) * R * l.nord * 16);
+  l.Ut = off;   off += static_cast<size_t>(4) * R * l.fin;
+  l.G = off;    off += static_cast<size_t>(24) * R * l.fout;
+  l.Xt = off;   off += static_cast<size_t>(24) * R * l.fin;
+  l.M = off;    off += static_cast<size_t>(4) * R * l.tser;
+  l.Ypt = off;  off += static_cast<size_t>(4) * R * l.b * l.tser;
+  l.Ypf = off;  off += static_cast<size_t>(4) * R * l.b * l.fin;
+  l.Z = off;    off += static_cast<size_t>(4) * R * l.fin;
+  l.total = off;
+  return l;
+}
+
+pm_status st(hipError_t e) { return e == hipSuccess ? PM_OK : PM_ERR_DEVICE; }
+
+// twist phases z_{mu nu}
+double2 twist(const nspt_params* p, int mu, int nu) {
+  const double ang = 2.0 * M_PI * p->k / p->L;
+  if (mu < nu) return make_double2(std::cos(ang), std::sin(ang));
+  return make_double2(std::cos(ang), -std::sin(ang));
+}
+
+// Accumulates GEMM jobs of one operand form and launches them in chunks.
+struct GemmBatch {
+  FourierType ft;
+  hipStream_t s;
+  int form;     // opA * 2 + opB
+  GemmArgs a{};
+  pm_status status = PM_OK;
+  void add(const void* A, const void* B, void* C, int n, int L) {
+    if (status) return;
+    if (a.njobs == kMaxGemmJobs) flush();
+    const int tile = gemm_tile(ft);
+    GemmJob& j = a.jobs[a.njobs++];
+    j.A = A;
+    j.B = B;
+    j.C = C;
+    j.n = n;
+    j.L = L;
+    j.opA = form >> 1;
+    j.opB = form & 1;
+    j.tiles_m = (n + tile - 1) / tile;
+    j.tiles_n = j.tiles_m;
+    j.tile_begin = a.total_tiles;
+    a.total_tiles += j.tiles_m * j.tiles_n * L;
+  }
+  void flush() {
+    if (status || a.njobs == 0) return;
+    status = st(launch_gemm(a, ft, s));
+    a.njobs = 0;
+    a.total_tiles = 0;
+  }
+};
+
+struct RetruncBatch {
+  const Layout* l;
+  FourierType fin, fout;
+  hipStream_t s;
+  RetruncArgs a{};
+  pm_status status = PM_OK;
+  void add(const void* src, void* dst, double2* tdst, const double2* addbase, size_t add_stride) {
+    if (status) return;
+    if (a.njobs == kMaxRetruncJobs) flush();
+    RetruncJob& j = a.jobs[a.njobs++];
+    j.src = src;
+    j.dst = dst;
+    j.tdst = tdst;
+    j.add = addbase;
+    j.add_stride = add_stride;
+    j.E = l->E;
+    j.n = l->n;
+    j.nord = l->nord;
+  }
+  void flush() {
+    if (status || a.njobs == 0) return;
+    status = st(launch_retrunc(a, l->L, l->E, fin, fout, s));
+    a.njobs = 0;
+  }
+};
+
 }  // namespace
 
 size_t nspt_workspace_bytes(int replicas, const nspt_params* p, int prec) {
   if (!valid_params(replicas, p, prec)) return 0;
-  const size_t E = static_cast<size_t>(p->n) * p->n;
-  return static_cast<size_t>(replicas) * 64 * (p->ntrunc + 1) * E * 16;
+  return layout(replicas, p, prec).total;
 }
 
-pm_status nspt_step(void* U, const void* eta, int replicas, const nspt_params* p, int prec,
-                    void* workspace, size_t workspace_bytes, hipStream_t) {
-  if (!valid_params(replicas, p, prec)) return PM_ERR_INVALID;
+pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int prec, void* workspace,
+                    size_t workspace_bytes, hipStream_t s) {
+  if (!valid_params(R, p, prec)) return PM_ERR_INVALID;
   if (!U || !eta || !workspace) return PM_ERR_INVALID;
-  if (workspace_bytes < nspt_workspace_bytes(replicas, p, prec)) return PM_ERR_WORKSPACE;
-  return PM_ERR_UNSUPPORTED;
+  if (reinterpret_cast<uintptr_t>(U) % 16 || reinterpret_cast<uintptr_t>(eta) % 16 ||
+      reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return PM_ERR_INVALID;
+  const Layout l = layout(R, p, prec);
+  if (workspace_bytes < l.total) return PM_ERR_WORKSPACE;
+  {
+    const uintptr_t wb = reinterpret_cast<uintptr_t>(workspace), we = wb + l.total;
+    const uintptr_t ub = reinterpret_cast<uintptr_t>(U), ue = ub + static_cast<size_t>(R) * 4 * l.nord * l.E * 16;
+    const uintptr_t nb = reinterpret_cast<uintptr_t>(eta), ne = nb + static_cast<size_t>(R) * 4 * l.E * 16;
+    if ((wb < ue && ub < we) || (wb < ne && nb < we) || (ub < ne && nb < ue)) return PM_ERR_INVALID;
+  }
+
+  char* ws = static_cast<char*>(workspace);
+  const FourierType fin = in_type(prec), fout = out_type(prec);
+  const int n = l.n, E = l.E, nord = l.nord, L = l.L, b = l.b;
+  ScaleRec* rec = reinterpret_cast<ScaleRec*>(ws + l.rec);
+  ScaleRec* unit = reinterpret_cast<ScaleRec*>(ws + l.unit);
+  double* part = reinterpret_cast<double*>(ws + l.part);
+  double2* trc = reinterpret_cast<double2*>(ws + l.trc);
+  double2* Ug = static_cast<double2*>(U);
+  const double2* etag = static_cast<const double2*>(eta);
+  const size_t series_elems = static_cast<size_t>(nord) * E;
+
+  auto Useries = [&](int r, int mu) { return Ug + (static_cast<size_t>(r) * 4 + mu) * series_elems; };
+  auto Ut = [&](int r, int mu) { return ws + l.Ut + (static_cast<size_t>(r) * 4 + mu) * l.fin; };
+  auto G = [&](int r, int slot) { return ws + l.G + (static_cast<size_t>(r) * 24 + slot) * l.fout; };
+  auto Xt = [&](int r, int slot) { return ws + l.Xt + (static_cast<size_t>(r) * 24 + slot) * l.fin; };
+  auto Mser = [&](int r, int mu) {
+    return reinterpret_cast<double2*>(ws + l.M + (static_cast<size_t>(r) * 4 + mu) * l.tser);
+  };
+  // powers Y^j, j = 1..b, slot j - 1
+  auto Ypt = [&](int r, int mu, int j) {
+    return reinterpret_cast<double2*>(ws + l.Ypt + ((static_cast<size_t>(r) * 4 + mu) * b + (j - 1)) * l.tser);
+  };
+  auto Ypf = [&](int r, int mu, int j) {
+    return ws + l.Ypf + ((static_cast<size_t>(r) * 4 + mu) * b + (j - 1)) * l.fin;
+  };
+  auto Zf = [&](int r, int mu) { return ws + l.Z + (static_cast<size_t>(r) * 4 + mu) * l.fin; };
+
+  // slot maps: Q_mn (m != n) -> 0..11, R_mn (m < n) -> 12..17, W_mn (m < n) -> 18..23
+  int qslot[4][4], pair[4][4];
+  {
+    int q = 0, pr = 0;
+    for (int m = 0; m < 4; ++m)
+      for (int nn = 0; nn < 4; ++nn) {
+        qslot[m][nn] = (m != nn) ? q++ : -1;
+        pair[m][nn] = (m < nn) ? pr++ : -1;
+      }
+  }
+
+  // ---- 1. rescale factor from the norms of all link series; unit record
+  {
+    NormArgs na{};
+    for (int r = 0; r < R; ++r)
+      for (int mu = 0; mu < 4; ++mu) {
+        if (na.njobs == kMaxTransformJobs) {
+          pm_status e = st(launch_norms(na, nord, s));
+          if (e) return e;
+          na.njobs = 0;
+        }
+        NormJob& j = na.jobs[na.njobs++];
+        j.src = Useries(r, mu);
+        j.partial = part + (static_cast<size_t>(r) * 4 + mu) * nord * kNormChunks;
+        j.E = E;
+        j.nord = nord;
+      }
+    pm_status e = st(launch_norms(na, nord, s));
+    if (e) return e;
+    ScaleArgs sa{};
+    sa.njobs = 2;
+    sa.jobs[0].partA = part;
+    sa.jobs[0].partB = part;
+    sa.jobs[0].rec = rec;
+    sa.jobs[0].nord = nord;
+    sa.jobs[0].L = L;
+    sa.jobs[0].fixed_s = 0.0;
+    sa.jobs[0].nser = 4 * R;
+    sa.jobs[1] = sa.jobs[0];
+    sa.jobs[1].rec = unit;
+    sa.jobs[1].fixed_s = 1.0;
+    sa.jobs[1].nser = 1;
+    e = st(launch_scale(sa, s));
+    if (e) return e;
+  }
+
+  // ---- 2. forward transforms of the links
+  {
+    FwdArgs fa{};
+    for (int r = 0; r < R; ++r)
+      for (int mu = 0; mu < 4; ++mu) {
+        if (fa.njobs == kMaxTransformJobs) {
+          pm_status e = st(launch_forward(fa, L, E, fin, s));
+          if (e) return e;
+          fa.njobs = 0;
+        }
+        FwdJob& j = fa.jobs[fa.njobs++];
+        j.src = Useries(r, mu);
+        j.dst = Ut(r, mu);
+        j.rec = rec;
+        j.E = E;
+        j.nord = nord;
+        j.n = n;
+      }
+    pm_status e = st(launch_forward(fa, L, E, fin, s));
+    if (e) return e;
+  }
+
+  // ---- 3. first staple wave: Q, R, W
+  {
+    GemmBatch nn{fin, s, 0}, nc{fin, s, 1}, cn{fin, s, 2};
+    for (int r = 0; r < R; ++r)
+      for (int m = 0; m < 4; ++m)
+        for (int q = 0; q < 4; ++q) {
+          if (m == q) continue;
+          nn.add(Ut(r, m), Ut(r, q), G(r, qslot[m][q]), n, L);
+          if (m < q) {
+            nc.add(Ut(r, m), Ut(r, q), G(r, 12 + pair[m][q]), n, L);
+            cn.add(Ut(r, m), Ut(r, q), G(r, 18 + pair[m][q]), n, L);
+          }
+        }
+    nn.flush();
+    nc.flush();
+    cn.flush();
+    if (nn.status || nc.status || cn.status) return PM_ERR_DEVICE;
+    RetruncBatch rt{&l, fout, fin, s};
+    rt.a.nadd = 0;
+    rt.a.idcoef = make_double2(0.0, 0.0);
+    for (int r = 0; r < R; ++r)
+      for (int slot = 0; slot < 24; ++slot) rt.add(G(r, slot), Xt(r, slot), nullptr, nullptr, 0);
+    rt.flush();
+    if (rt.status) return rt.status;
+  }
+
+  // ---- 4. second staple wave: P (6) into G slots 0..5, T (12) into G slots 6..17
+  {
+    GemmBatch nc{fin, s, 1}, nn{fin, s, 0}, cc{fin, s, 3};
+    for (int r = 0; r < R; ++r)
+      for (int m = 0; m < 4; ++m)
+        for (int q = 0; q < 4; ++q) {
+          if (m == q) continue;
+          if (m < q) {
+            nc.add(Xt(r, qslot[m][q]), Xt(r, qslot[q][m]), G(r, pair[m][q]), n, L);          // P_mq
+            nn.add(Xt(r, 12 + pair[m][q]), Xt(r, 18 + pair[m][q]), G(r, 6 + qslot[m][q]), n, L);  // T_mq
+          } else {
+            cc.add(Xt(r, 12 + pair[q][m]), Xt(r, 18 + pair[q][m]), G(r, 6 + qslot[m][q]), n, L);  // T_mq, m > q
+          }
+        }
+    nc.flush();
+    nn.flush();
+    cc.flush();
+    if (nn.status || nc.status || cc.status) return PM_ERR_DEVICE;
+  }
+
+  // ---- 5. M_m: weighted sum of P and T, back to the (unscaled) time domain
+  {
+    CombineArgs ca{};
+    auto flush = [&]() -> pm_status {
+      if (ca.njobs == 0) return PM_OK;
+      pm_status e = st(launch_inv_combine(ca, L, E, fout, s));
+      ca.njobs = 0;
+      return e;
+    };
+    for (int r = 0; r < R; ++r)
+      for (int m = 0; m < 4; ++m) {
+        if (ca.njobs == kMaxCombineJobs) { pm_status e = flush(); if (e) return e; }
+        CombineJob& j = ca.jobs[ca.njobs++];
+        j.nsrc = 0;
+        for (int q = 0; q < 4; ++q) {
+          if (q == m) continue;
+          if (q > m) {
+            j.src[j.nsrc] = G(r, pair[m][q]);
+            j.coef[j.nsrc++] = twist(p, m, q);
+          } else {
+            const double2 z = twist(p, q, m);
+            j.src[j.nsrc] = G(r, pair[q][m]);
+            j.coef[j.nsrc++] = make_double2(-z.x, -z.y);
+          }
+          const double2 z = twist(p, m, q);
+          j.src[j.nsrc] = G(r, 6 + qslot[m][q]);
+          j.coef[j.nsrc++] = make_double2(z.x, -z.y);
+        }
+        j.dst = Mser(r, m);
+        j.rec = rec;
+        j.E = E;
+        j.nord = nord;
+        j.kmin = 0;
+      }
+    pm_status e = flush();
+    if (e) return e;
+  }
+
+  // ---- 6. traces and the drift-plus-noise exponent Y (scaled), Y^1 = Y
+  {
+    TraceArgs ta{};
+    for (int r = 0; r < R; ++r)
+      for (int m = 0; m < 4; ++m) {
+        if (ta.njobs == kMaxTransformJobs) {
+          pm_status e = st(launch_trace(ta, nord, s));
+          if (e) return e;
+          ta.njobs = 0;
+        }
+        TraceJob& j = ta.jobs[ta.njobs++];
+        j.src = Mser(r, m);
+        j.out = trc + (static_cast<size_t>(r) * 4 + m) * nord;
+        j.n = n;
+        j.nord = nord;
+      }
+    pm_status e = st(launch_trace(ta, nord, s));
+    if (e) return e;
+    ForceArgs fa{};
+    fa.eps = p->eps;
+    fa.noise_amp = std::sqrt(2.0 * p->eps);
+    for (int r = 0; r < R; ++r)
+      for (int m = 0; m < 4; ++m) {
+        if (fa.njobs == kMaxForceJobs) {
+          e = st(launch_force(fa, n, nord, s));
+          if (e) return e;
+          fa.njobs = 0;
+        }
+        ForceJob& j = fa.jobs[fa.njobs++];
+        j.M = Mser(r, m);
+        j.tr = trc + (static_cast<size_t>(r) * 4 + m) * nord;
+        j.eta = etag + (static_cast<size_t>(r) * 4 + m) * E;
+        j.Y = Ypt(r, m, 1);
+        j.rec = rec;
+        j.n = n;
+        j.nord = nord;
+      }
+    e = st(launch_force(fa, n, nord, s));
+    if (e) return e;
+    // Fourier coefficients of Y (already scaled: unit record)
+    FwdArgs fw{};
+    for (int r = 0; r < R; ++r)
+      for (int m = 0; m < 4; ++m) {
+        if (fw.njobs == kMaxTransformJobs) {
+          e = st(launch_forward(fw, L, E, fin, s));
+          if (e) return e;
+          fw.njobs = 0;
+        }
+        FwdJob& j = fw.jobs[fw.njobs++];
+        j.src = Ypt(r, m, 1);
+        j.dst = Ypf(r, m, 1);
+        j.rec = unit;
+        j.E = E;
+        j.nord = nord;
+        j.n = n;
+      }
+    e = st(launch_forward(fw, L, E, fin, s));
+    if (e) return e;
+  }
+
+  // ---- 7. powers Y^2 .. Y^b
+  for (int j = 2; j <= b; ++j) {
+    GemmBatch g{fin, s, 0};
+    for (int r = 0; r < R; ++r)
+      for (int m = 0; m < 4; ++m) g.add(Ypf(r, m, j - 1), Ypf(r, m, 1), G(r, m), n, L);
+    g.flush();
+    if (g.status) return g.status;
+    RetruncBatch rt{&l, fout, fin, s};
+    rt.a.nadd = 0;
+    rt.a.idcoef = make_double2(0.0, 0.0);
+    for (int r = 0; r < R; ++r)
+      for (int m = 0; m < 4; ++m) rt.add(G(r, m), Ypf(r, m, j), Ypt(r, m, j), nullptr, 0);
+    rt.flush();
+    if (rt.status) return rt.status;
+  }
+
+  // ---- 8. E = sum_q (Y^b)^q B_q(Y) by Horner in Y^b
+  {
+    const int nt = nord - 1;
+    const int Q = nt / b;
+    auto cfac = [&](int jj) {
+      if (jj > nt) return 0.0;
+      double f = 1.0;
+      for (int t = 2; t <= jj; ++t) f *= t;
+      return 1.0 / f;
+    };
+    const size_t ystride = l.tser / sizeof(double2);   // elements between Y^i and Y^(i+1)
+    for (int q = Q; q >= 0; --q) {
+      if (q < Q) {
+        GemmBatch g{fin, s, 0};
+        for (int r = 0; r < R; ++r)
+          for (int m = 0; m < 4; ++m) g.add(Ypf(r, m, b), Zf(r, m), G(r, m), n, L);
+        g.flush();
+        if (g.status) return g.status;
+      }
+      RetruncBatch rt{&l, fout, fin, s};
+      rt.a.nadd = b - 1;
+      for (int i = 1; i < b; ++i) rt.a.coef[i - 1] = make_double2(cfac(q * b + i), 0.0);
+      rt.a.idcoef = make_double2(cfac(q * b), 0.0);
+      for (int r = 0; r < R; ++r)
+        for (int m = 0; m < 4; ++m)
+          rt.add(q < Q ? static_cast<const void*>(G(r, m)) : nullptr, Zf(r, m), nullptr,
+                 b > 1 ? Ypt(r, m, 1) : nullptr, ystride);
+      rt.flush();
+      if (rt.status) return rt.status;
+    }
+  }
+
+  // ---- 9. link update U_m <- E_m * U_m (orders >= 1)
+  {
+    GemmBatch g{fin, s, 0};
+    for (int r = 0; r < R; ++r)
+      for (int m = 0; m < 4; ++m) g.add(Zf(r, m), Ut(r, m), G(r, m), n, L);
+    g.flush();
+    if (g.status) return g.status;
+    CombineArgs ca{};
+    for (int r = 0; r < R; ++r)
+      for (int m = 0; m < 4; ++m) {
+        if (ca.njobs == kMaxCombineJobs) {
+          pm_status e = st(launch_inv_combine(ca, L, E, fout, s));
+          if (e) return e;
+          ca.njobs = 0;
+        }
+        CombineJob& j = ca.jobs[ca.njobs++];
+        j.nsrc = 1;
+        j.src[0] = G(r, m);
+        j.coef[0] = make_double2(1.0, 0.0);
+        j.dst = Useries(r, m);
+        j.rec = rec;
+        j.E = E;
+        j.nord = nord;
+        j.kmin = 1;
+      }
+    pm_status e = st(launch_inv_combine(ca, L, E, fout, s));
+    if (e) return e;
+  }
+  return PM_OK;
 }
 
 }  // namespace pm

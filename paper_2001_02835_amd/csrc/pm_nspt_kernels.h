@@ -1,0 +1,72 @@
+// Launch interface of the NSPT-specific kernels (pm_nspt_kernels.hip).
+#pragma once
+
+#include "pm_kernels.h"
+
+namespace pm {
+
+constexpr int kMaxAdd = 8;
+
+// Re-truncation of a Fourier-space product (see pm_nspt_kernels.hip).
+struct RetruncJob {
+  const void* src;         // [L][E] product (FP64/FP32), or null for "no product"
+  void* dst;               // [L][E] Fourier output in the product-input format
+  double2* tdst;           // optional [nord][E] time-domain output (same scaling)
+  const double2* add;      // addend a (a < nadd) at add + a * add_stride: [nord][E]
+  size_t add_stride;       // elements between consecutive addends
+  int E;
+  int n;
+  int nord;
+  int pad_;
+};
+constexpr int kMaxRetruncJobs = 48;
+struct RetruncArgs {
+  RetruncJob jobs[kMaxRetruncJobs];
+  double2 coef[kMaxAdd];   // addend weights (shared by the jobs of a launch)
+  double2 idcoef;          // weight of the unit series
+  int nadd;
+  int njobs;
+};
+
+// Inverse transform of sum_q coef[q] * src[q], unscaled, orders kmin..nord-1.
+constexpr int kMaxCombine = 6;
+struct CombineJob {
+  const void* src[kMaxCombine];
+  double2 coef[kMaxCombine];
+  double2* dst;
+  const ScaleRec* rec;
+  int nsrc;
+  int E;
+  int nord;
+  int kmin;
+};
+constexpr int kMaxCombineJobs = 16;
+struct CombineArgs { CombineJob jobs[kMaxCombineJobs]; int njobs; };
+
+struct TraceJob {
+  const double2* src;      // [nord][n][n]
+  double2* out;            // [nord]
+  int n;
+  int nord;
+};
+struct TraceArgs { TraceJob jobs[kMaxTransformJobs]; int njobs; };
+
+struct ForceJob {
+  const double2* M;        // [nord][n][n], unscaled
+  const double2* tr;       // [nord] traces of M
+  const double2* eta;      // [n][n] noise
+  double2* Y;              // [nord][n][n] output, multiplied by s^k
+  const ScaleRec* rec;
+  int n;
+  int nord;
+};
+constexpr int kMaxForceJobs = 48;
+struct ForceArgs { ForceJob jobs[kMaxForceJobs]; double eps; double noise_amp; int njobs; };
+
+hipError_t launch_retrunc(const RetruncArgs& a, int L, int max_entries, FourierType fin, FourierType fout,
+                          hipStream_t s);
+hipError_t launch_inv_combine(const CombineArgs& a, int L, int max_entries, FourierType fin, hipStream_t s);
+hipError_t launch_trace(const TraceArgs& a, int max_nord, hipStream_t s);
+hipError_t launch_force(const ForceArgs& a, int n, int max_nord, hipStream_t s);
+
+}  // namespace pm

@@ -1,0 +1,215 @@
+// Kernels of the NSPT Euler-Langevin step (TEK model, eqs. (2)-(3)) that are
+// not plain series products:
+//
+//  * k_retrunc      - re-truncation of a product kept in Fourier space:
+//                     inverse transform, drop the orders above ntrunc, add a
+//                     linear combination of truncated series (and of the
+//                     unit series), forward transform again.  A chain of
+//                     star products stays in Fourier space this way, one
+//                     HBM read and write per link of the chain.
+//  * k_inv_combine  - inverse transform of a weighted sum of products
+//                     (the staple combination), with 1/L and unscaling.
+//  * k_trace        - Tr M^(k) for every order.
+//  * k_force        - D = M - M^+, F = i (D - Tr D / N), and the
+//                     drift-plus-noise exponent Y = i X = i (eps F + sqrt(2 eps) eta g),
+//                     rescaled by s^k for the following products.
+//
+// All series here are FP64 complex [nord][n][n]; Fourier coefficients use the
+// formats of the product kernels (FP64, FP32 or split BF16).
+#include "pm_fft.h"
+#include "pm_nspt_kernels.h"
+
+namespace pm {
+
+namespace {
+
+// ----------------------------------------------------------- re-truncation
+
+template <int L, FourierType FIN, FourierType FOUT>
+__global__ __launch_bounds__(kFftThreads) void k_retrunc(RetruncArgs args) {
+  __shared__ double2 acc[L / 2][kEnt];
+  const RetruncJob& jb = args.jobs[blockIdx.y];
+  const int E = jb.E;
+  const int e0 = blockIdx.x * kEnt;
+  if (e0 >= E) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int r = threadIdx.x / kWave;
+  const int e = e0 + lane;
+  const bool valid = e < E;
+  const int nord = jb.nord;
+  if (jb.src) {
+    auto load = [&](int p) { return valid ? load_mode<FIN>(jb.src, E, p, e) : make_double2(0.0, 0.0); };
+    inverse_to_lds<L>(load, acc, nord, lane, r);
+  }
+  // time-domain value of order k: (1/L) inverse + addends (+ identity at order 0)
+  const int n = jb.n;
+  const bool diag = valid && (e / n) == (e - (e / n) * n);
+  for (int k = r; k < nord; k += 4) {
+    double2 x = jb.src ? cscale(acc[k][lane], 1.0 / L) : make_double2(0.0, 0.0);
+    if (valid) {
+      for (int a = 0; a < args.nadd; ++a) {
+        const double2 y = jb.add[static_cast<size_t>(a) * jb.add_stride + static_cast<size_t>(k) * E + e];
+        x = cadd(x, cmul(args.coef[a], y));
+      }
+      if (k == 0 && diag) x = cadd(x, args.idcoef);
+      if (jb.tdst) jb.tdst[static_cast<size_t>(k) * E + e] = x;
+    }
+    acc[k][lane] = x;
+  }
+  __syncthreads();
+  forward_from_tile<L, FOUT>(acc, nord, lane, r, jb.dst, E, n, e, valid);
+}
+
+// --------------------------------------------- inverse of a weighted sum
+
+template <int L, FourierType FIN>
+__global__ __launch_bounds__(kFftThreads) void k_inv_combine(CombineArgs args) {
+  __shared__ double2 acc[L / 2][kEnt];
+  const CombineJob& jb = args.jobs[blockIdx.y];
+  const int E = jb.E;
+  const int e0 = blockIdx.x * kEnt;
+  if (e0 >= E) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int r = threadIdx.x / kWave;
+  const int e = e0 + lane;
+  const bool valid = e < E;
+  auto load = [&](int p) {
+    double2 v = make_double2(0.0, 0.0);
+    if (valid)
+      for (int q = 0; q < jb.nsrc; ++q) v = cadd(v, cmul(jb.coef[q], load_mode<FIN>(jb.src[q], E, p, e)));
+    return v;
+  };
+  inverse_to_lds<L>(load, acc, jb.nord, lane, r);
+  if (valid)
+    for (int k = r; k < jb.nord; k += 4)
+      if (k >= jb.kmin) jb.dst[static_cast<size_t>(k) * E + e] = cscale(acc[k][lane], jb.rec->sinv[k]);
+}
+
+// ------------------------------------------------------------------ trace
+
+__global__ __launch_bounds__(64) void k_trace(TraceArgs args) {
+  const TraceJob& jb = args.jobs[blockIdx.y];
+  const int k = blockIdx.x;
+  if (k >= jb.nord) return;
+  const int n = jb.n;
+  const double2* m = jb.src + static_cast<size_t>(k) * n * n;
+  double2 s = make_double2(0.0, 0.0);
+  for (int i = threadIdx.x; i < n; i += 64) s = cadd(s, m[static_cast<size_t>(i) * n + i]);
+  // fixed-order wave reduction
+  for (int off = 32; off > 0; off >>= 1) {
+    s.x += __shfl_down(s.x, off);
+    s.y += __shfl_down(s.y, off);
+  }
+  if (threadIdx.x == 0) jb.out[k] = s;
+}
+
+// ------------------------------------------------------------------ force
+
+// One 32 x 32 tile (I, J) of one order k: the mirrored tile (J, I) is staged
+// through LDS so that both M and M^+ are read with coalesced loads.
+constexpr int kTile = 32;
+
+__global__ __launch_bounds__(256) void k_force(ForceArgs args) {
+  __shared__ double2 mir[kTile][kTile + 1];
+  const ForceJob& jb = args.jobs[blockIdx.z];
+  const int k = blockIdx.y;
+  const int n = jb.n;
+  const int nt = (n + kTile - 1) / kTile;
+  if (k >= jb.nord || static_cast<int>(blockIdx.x) >= nt * nt) return;
+  const int ti = blockIdx.x / nt, tj = blockIdx.x - (blockIdx.x / nt) * nt;
+  const int I0 = ti * kTile, J0 = tj * kTile;
+  const size_t E = static_cast<size_t>(n) * n;
+  const double2* Mk = jb.M + static_cast<size_t>(k) * E;
+  double2* Yk = jb.Y + static_cast<size_t>(k) * E;
+  const int tx = threadIdx.x & (kTile - 1), ty = threadIdx.x / kTile;   // 32 x 8
+  // stage M[J0 + a][I0 + b] at mir[a][b]
+  for (int a = ty; a < kTile; a += 8) {
+    const int gi = J0 + a, gj = I0 + tx;
+    mir[a][tx] = (gi < n && gj < n) ? Mk[static_cast<size_t>(gi) * n + gj] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const double scale = jb.rec->spow[k];
+  const double eps = args.eps;
+  const double2 tr = jb.tr[k];
+  const double noise = args.noise_amp;   // sqrt(2 eps)
+  for (int a = ty; a < kTile; a += 8) {
+    const int i = I0 + a, j = J0 + tx;
+    if (i >= n || j >= n) continue;
+    double2 y = make_double2(0.0, 0.0);
+    if (k >= 1) {
+      const double2 mij = Mk[static_cast<size_t>(i) * n + j];
+      const double2 mji = mir[tx][a];                 // M[j][i]
+      // D = M - M^+; Tr D = 2 i Im Tr M
+      double2 d = make_double2(mij.x - mji.x, mij.y + mji.y);
+      if (i == j) d.y -= 2.0 * tr.y / n;
+      y = make_double2(-eps * d.x, -eps * d.y);       // i X = -eps (D - Tr D / N)
+      if (k == 1) {
+        const double2 et = jb.eta[static_cast<size_t>(i) * n + j];
+        y = make_double2(y.x - noise * et.y, y.y + noise * et.x);   // + i sqrt(2 eps) eta
+      }
+      y = cscale(y, scale);
+    }
+    Yk[static_cast<size_t>(i) * n + j] = y;
+  }
+}
+
+template <FourierType FIN, FourierType FOUT>
+hipError_t retrunc_dispatch(const RetruncArgs& a, int L, dim3 g, hipStream_t s) {
+  switch (L) {
+    case 4: k_retrunc<4, FIN, FOUT><<<g, kFftThreads, 0, s>>>(a); break;
+    case 8: k_retrunc<8, FIN, FOUT><<<g, kFftThreads, 0, s>>>(a); break;
+    case 16: k_retrunc<16, FIN, FOUT><<<g, kFftThreads, 0, s>>>(a); break;
+    case 32: k_retrunc<32, FIN, FOUT><<<g, kFftThreads, 0, s>>>(a); break;
+    case 64: k_retrunc<64, FIN, FOUT><<<g, kFftThreads, 0, s>>>(a); break;
+    case 128: k_retrunc<128, FIN, FOUT><<<g, kFftThreads, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <FourierType FIN>
+hipError_t combine_dispatch(const CombineArgs& a, int L, dim3 g, hipStream_t s) {
+  switch (L) {
+    case 4: k_inv_combine<4, FIN><<<g, kFftThreads, 0, s>>>(a); break;
+    case 8: k_inv_combine<8, FIN><<<g, kFftThreads, 0, s>>>(a); break;
+    case 16: k_inv_combine<16, FIN><<<g, kFftThreads, 0, s>>>(a); break;
+    case 32: k_inv_combine<32, FIN><<<g, kFftThreads, 0, s>>>(a); break;
+    case 64: k_inv_combine<64, FIN><<<g, kFftThreads, 0, s>>>(a); break;
+    case 128: k_inv_combine<128, FIN><<<g, kFftThreads, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_retrunc(const RetruncArgs& a, int L, int max_entries, FourierType fin, FourierType fout,
+                          hipStream_t s) {
+  if (a.njobs <= 0) return hipSuccess;
+  dim3 g((max_entries + kEnt - 1) / kEnt, a.njobs);
+  if (fin == kF64) return retrunc_dispatch<kF64, kF64>(a, L, g, s);
+  if (fout == kF32) return retrunc_dispatch<kF32, kF32>(a, L, g, s);
+  return retrunc_dispatch<kF32, kBF16Split>(a, L, g, s);
+}
+
+hipError_t launch_inv_combine(const CombineArgs& a, int L, int max_entries, FourierType fin, hipStream_t s) {
+  if (a.njobs <= 0) return hipSuccess;
+  dim3 g((max_entries + kEnt - 1) / kEnt, a.njobs);
+  if (fin == kF64) return combine_dispatch<kF64>(a, L, g, s);
+  return combine_dispatch<kF32>(a, L, g, s);
+}
+
+hipError_t launch_trace(const TraceArgs& a, int max_nord, hipStream_t s) {
+  if (a.njobs <= 0) return hipSuccess;
+  k_trace<<<dim3(max_nord, a.njobs), 64, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_force(const ForceArgs& a, int n, int max_nord, hipStream_t s) {
+  if (a.njobs <= 0) return hipSuccess;
+  const int nt = (n + kTile - 1) / kTile;
+  k_force<<<dim3(nt * nt, max_nord, a.njobs), 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace pm

@@ -18,102 +18,14 @@
 // DFT d_r, and the four residues are combined as
 //   C[k] = (1/L) sum_r w_L^{-kr} d_r[k mod M]   (k < nord)
 // through LDS in a fixed order, so results are bitwise reproducible.
-#include "pm_common.h"
-#include "pm_kernels.h"
-
-#include <hip/hip_bfloat16.h>
+#include "pm_fft.h"
 
 namespace pm {
 
 namespace {
 
-constexpr int kEnt = 64;        // entries per work-group
-constexpr int kThreads = 256;   // four wavefronts
-
-// --------------------------------------------------------------- stores
-
-__device__ __forceinline__ uint16_t bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  uint32_t lsb = (u >> 16) & 1u;
-  u += 0x7fffu + lsb;
-  return static_cast<uint16_t>(u >> 16);
-}
-__device__ __forceinline__ double bf16_to_double(uint16_t h) {
-  return static_cast<double>(__uint_as_float(static_cast<uint32_t>(h) << 16));
-}
-// hi = RNE_bf16(x), lo = RNE_bf16(x - hi) with x - hi exact in FP64.
-__device__ __forceinline__ void split_bf16(double x, uint16_t& hi, uint16_t& lo) {
-  hi = bf16_rne(static_cast<float>(x));
-  double r = x - bf16_to_double(hi);
-  lo = bf16_rne(static_cast<float>(r));
-}
-
-// BF16 split layout of one mode: four planes (re_hi, re_lo, im_hi, im_lo),
-// each row-major [n][ld] with ld = n rounded up to a multiple of 8, so that a
-// lane of the product kernel can fetch 8 consecutive entries of a row with a
-// single 16-byte load.  The padding columns are never written (the product
-// kernel masks them).
-__device__ __forceinline__ size_t bf16_plane_elems(int n) { return static_cast<size_t>(bf16_ld(n)) * n; }
-
-template <FourierType FT>
-__device__ __forceinline__ void store_mode(const FwdJob& jb, int p, int e, double2 v) {
-  if constexpr (FT == kF64) {
-    reinterpret_cast<double2*>(jb.dst)[static_cast<size_t>(p) * jb.E + e] = v;
-  } else if constexpr (FT == kF32) {
-    reinterpret_cast<float2*>(jb.dst)[static_cast<size_t>(p) * jb.E + e] =
-        make_float2(static_cast<float>(v.x), static_cast<float>(v.y));
-  } else {
-    const int n = jb.n;
-    const int i = e / n, j = e - (e / n) * n;
-    const size_t plane = bf16_plane_elems(n);
-    uint16_t* base = reinterpret_cast<uint16_t*>(jb.dst) + static_cast<size_t>(p) * 4 * plane;
-    const size_t off = static_cast<size_t>(i) * bf16_ld(n) + j;
-    uint16_t rh, rl, ih, il;
-    split_bf16(v.x, rh, rl);
-    split_bf16(v.y, ih, il);
-    base[off] = rh;
-    base[plane + off] = rl;
-    base[2 * plane + off] = ih;
-    base[3 * plane + off] = il;
-  }
-}
-
-template <FourierType FT>
-__device__ __forceinline__ double2 load_mode(const InvJob& jb, int p, int e) {
-  if constexpr (FT == kF64) {
-    return reinterpret_cast<const double2*>(jb.src)[static_cast<size_t>(p) * jb.E + e];
-  } else {
-    float2 f = reinterpret_cast<const float2*>(jb.src)[static_cast<size_t>(p) * jb.E + e];
-    return make_double2(f.x, f.y);
-  }
-}
-
-// ------------------------------------------------------------ forward
-
-template <int L, int R, FourierType FT>
-__device__ __forceinline__ void forward_residue(const FwdJob& jb, const double2 (*tile)[kEnt],
-                                                int lane, int e, bool valid) {
-  constexpr int M = L / 4;
-  const int nord = jb.nord;
-  double2 c[M];
-  static_for<0, M>([&](auto mi) {
-    constexpr int m = decltype(mi)::value;
-    double2 a0 = (m < nord) ? tile[m][lane] : make_double2(0.0, 0.0);
-    double2 a1 = (m + M < nord) ? tile[m + M][lane] : make_double2(0.0, 0.0);
-    double2 t = cadd(a0, cmul_ipow<R>(a1));
-    c[m] = ctwiddle<m * R, L, +1>(t);
-  });
-  dft_inplace<M, +1>(c);
-  if (valid) {
-    static_for<0, M>([&](auto qi) {
-      constexpr int q = decltype(qi)::value;
-      store_mode<FT>(jb, 4 * q + R, e, c[q]);
-    });
-  }
-}
-
 template <int L, FourierType FT>
-__global__ __launch_bounds__(kThreads) void k_forward(FwdArgs args) {
+__global__ __launch_bounds__(kFftThreads) void k_forward(FwdArgs args) {
   __shared__ double2 tile[L / 2][kEnt];
   const FwdJob& jb = args.jobs[blockIdx.y];
   const int e0 = blockIdx.x * kEnt;
@@ -123,73 +35,17 @@ __global__ __launch_bounds__(kThreads) void k_forward(FwdArgs args) {
   const int e = e0 + lane;
   const bool valid = e < jb.E;
   // Step 1 fused: rescale by s^k while staging orders k = r, r+4, ...; the
-  // zero padding is never stored (orders >= nord read as zero below).
+  // zero padding is never stored (orders >= nord read as zero).
   for (int k = r; k < jb.nord; k += 4) {
     double2 v = valid ? jb.src[static_cast<size_t>(k) * jb.E + e] : make_double2(0.0, 0.0);
     tile[k][lane] = cscale(v, jb.rec->spow[k]);
   }
   __syncthreads();
-  switch (r) {
-    case 0: forward_residue<L, 0, FT>(jb, tile, lane, e, valid); break;
-    case 1: forward_residue<L, 1, FT>(jb, tile, lane, e, valid); break;
-    case 2: forward_residue<L, 2, FT>(jb, tile, lane, e, valid); break;
-    default: forward_residue<L, 3, FT>(jb, tile, lane, e, valid); break;
-  }
-}
-
-// ------------------------------------------------------------ inverse
-
-template <int L, int R, FourierType FT>
-__device__ __forceinline__ void inverse_residue(const InvJob& jb, double2 (*acc)[kEnt], int lane, int e,
-                                                bool valid) {
-  constexpr int M = L / 4;
-  const int nord = jb.nord;
-  double2 d[M];
-  static_for<0, M>([&](auto qi) {
-    constexpr int q = decltype(qi)::value;
-    d[q] = valid ? load_mode<FT>(jb, 4 * q + R, e) : make_double2(0.0, 0.0);
-  });
-  dft_inplace<M, -1>(d);
-  // t_r[k] = w^{-kr} d_r[k mod M]; for k = j + M the extra factor is (-i)^r.
-  auto term = [&](auto ki) {
-    constexpr int k = decltype(ki)::value;
-    return ctwiddle<k * R, L, -1>(d[k % M]);
-  };
-  // Fixed-order accumulation: r = 0 writes, r = 1, 2 add, r = 3 finishes.
-  if constexpr (R == 0) {
-    static_for<0, 2 * M>([&](auto ki) {
-      constexpr int k = decltype(ki)::value;
-      if (k < nord) acc[k][lane] = term(ki);
-    });
-  }
-  __syncthreads();
-  if constexpr (R == 1) {
-    static_for<0, 2 * M>([&](auto ki) {
-      constexpr int k = decltype(ki)::value;
-      if (k < nord) acc[k][lane] = cadd(acc[k][lane], term(ki));
-    });
-  }
-  __syncthreads();
-  if constexpr (R == 2) {
-    static_for<0, 2 * M>([&](auto ki) {
-      constexpr int k = decltype(ki)::value;
-      if (k < nord) acc[k][lane] = cadd(acc[k][lane], term(ki));
-    });
-  }
-  __syncthreads();
-  if constexpr (R == 3) {
-    static_for<0, 2 * M>([&](auto ki) {
-      constexpr int k = decltype(ki)::value;
-      if (k < nord && valid) {
-        double2 v = cadd(acc[k][lane], term(ki));
-        jb.dst[static_cast<size_t>(k) * jb.E + e] = cscale(v, jb.rec->sinv[k]);
-      }
-    });
-  }
+  forward_from_tile<L, FT>(tile, jb.nord, lane, r, jb.dst, jb.E, jb.n, e, valid);
 }
 
 template <int L, FourierType FT>
-__global__ __launch_bounds__(kThreads) void k_inverse(InvArgs args) {
+__global__ __launch_bounds__(kFftThreads) void k_inverse(InvArgs args) {
   __shared__ double2 acc[L / 2][kEnt];
   const InvJob& jb = args.jobs[blockIdx.y];
   const int e0 = blockIdx.x * kEnt;
@@ -198,12 +54,12 @@ __global__ __launch_bounds__(kThreads) void k_inverse(InvArgs args) {
   const int r = threadIdx.x / kWave;
   const int e = e0 + lane;
   const bool valid = e < jb.E;
-  switch (r) {
-    case 0: inverse_residue<L, 0, FT>(jb, acc, lane, e, valid); break;
-    case 1: inverse_residue<L, 1, FT>(jb, acc, lane, e, valid); break;
-    case 2: inverse_residue<L, 2, FT>(jb, acc, lane, e, valid); break;
-    default: inverse_residue<L, 3, FT>(jb, acc, lane, e, valid); break;
-  }
+  auto load = [&](int p) { return valid ? load_mode<FT>(jb.src, jb.E, p, e) : make_double2(0.0, 0.0); };
+  inverse_to_lds<L>(load, acc, jb.nord, lane, r);
+  // Steps 4-5: 1/L, unscale by s^-k (one table), keep orders < nord
+  if (valid)
+    for (int k = r; k < jb.nord; k += 4)
+      jb.dst[static_cast<size_t>(k) * jb.E + e] = cscale(acc[k][lane], jb.rec->sinv[k]);
 }
 
 // ------------------------------------------------------------ norms / scale
@@ -242,10 +98,13 @@ __global__ __launch_bounds__(256) void k_norms(NormArgs args) {
 // spacing by 32 each.
 constexpr double kAbsent = 1e300;
 
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
 __global__ __launch_bounds__(64) void k_scale(ScaleArgs args) {
-  __shared__ double na[kMaxL / 2], nb[kMaxL / 2];
-  __shared__ double lmax[kMaxL], lmin[kMaxL / 2];
-  __shared__ double fval[64];
   const ScaleJob& jb = args.jobs[blockIdx.x];
   const int nord = jb.nord;
   const int tid = threadIdx.x;
@@ -253,48 +112,57 @@ __global__ __launch_bounds__(64) void k_scale(ScaleArgs args) {
   if (jb.fixed_s > 0.0) {
     t = log(jb.fixed_s);
   } else if (nord > 1) {
+    // per-order norms: lane k holds a_k, b_k (k < nord <= 64)
+    double na = 0.0, nb = 0.0;
     if (tid < nord) {
       double sa = 0.0, sb = 0.0;
-      for (int c = 0; c < kNormChunks; ++c) {
-        sa += jb.partA[tid * kNormChunks + c];
-        sb += jb.partB[tid * kNormChunks + c];
-      }
-      na[tid] = sqrt(sa);
-      nb[tid] = sqrt(sb);
+      for (int q = 0; q < jb.nser; ++q)
+        for (int c = 0; c < kNormChunks; ++c) {
+          sa += jb.partA[(q * nord + tid) * kNormChunks + c];
+          sb += jb.partB[(q * nord + tid) * kNormChunks + c];
+        }
+      na = sqrt(sa);
+      nb = sqrt(sb);
     }
-    __syncthreads();
+    // c_m = sum_j a_j b_{m-j}: lane m holds c_m (m < 64) and c_{m+64}
+    double c0 = 0.0, c1 = 0.0;
     const int nm = 2 * nord - 1;
-    for (int m = tid; m < nm; m += 64) {
-      double c = 0.0;
-      const int j0 = max(0, m - (nord - 1)), j1 = min(m, nord - 1);
-      for (int j = j0; j <= j1; ++j) c = fma(na[j], nb[m - j], c);
-      const bool ok = c > 0.0 && isfinite(c);
-      const double lc = ok ? log(c) : 0.0;
-      lmax[m] = ok ? lc : -kAbsent;
-      if (m < nord) lmin[m] = ok ? lc : kAbsent;
+    for (int j = 0; j < nord; ++j) {
+      const double aj = lane_value(na, j);
+      const int m0 = tid - j, m1 = tid + 64 - j;
+      // b_{m-j}: fetch from lane (m - j) when it is a valid order
+      const double b0 = __shfl(nb, m0 >= 0 && m0 < nord ? m0 : 0);
+      const double b1 = __shfl(nb, m1 >= 0 && m1 < nord ? m1 : 0);
+      if (m0 >= 0 && m0 < nord) c0 = fma(aj, b0, c0);
+      if (m1 >= 0 && m1 < nord && tid + 64 < nm) c1 = fma(aj, b1, c1);
     }
-    __syncthreads();
-    bool any = false;
-    for (int k = 0; k < nord; ++k) any |= lmin[k] < kAbsent;
+    const bool ok0 = tid < nm && c0 > 0.0 && isfinite(c0);
+    const bool ok1 = tid + 64 < nm && c1 > 0.0 && isfinite(c1);
+    const double lc0 = ok0 ? log(c0) : 0.0, lc1 = ok1 ? log(c1) : 0.0;
+    const double lmax0 = ok0 ? lc0 : -kAbsent, lmax1 = ok1 ? lc1 : -kAbsent;
+    const double lmin0 = (ok0 && tid < nord) ? lc0 : kAbsent;
+    const bool any = __any(ok0 && tid < nord);
     if (any) {
       double lo = -300.0 / (2.0 * (nord - 1)), hi = -lo;
       for (int round = 0; round < 3; ++round) {
         const double step = (hi - lo) / 63.0;
         const double tt = lo + step * tid;
         double mx = -kAbsent, mn = kAbsent;
-        for (int m = 0; m < nord; ++m) {
-          mx = fmax(mx, fma(static_cast<double>(m), tt, lmax[m]));
-          mn = fmin(mn, fma(static_cast<double>(m), tt, lmin[m]));
+        for (int m = 0; m < 64; ++m) {
+          const double x = lane_value(lmax0, m), y = lane_value(lmin0, m);
+          mx = fmax(mx, fma(static_cast<double>(m), tt, x));
+          mn = fmin(mn, fma(static_cast<double>(m), tt, y));
         }
-        for (int m = nord; m < nm; ++m) mx = fmax(mx, fma(static_cast<double>(m), tt, lmax[m]));
-        fval[tid] = mx - mn;
-        __syncthreads();
-        int best = 0;
-        double fb = fval[0];
-        for (int i = 1; i < 64; ++i)
-          if (fval[i] < fb) { fb = fval[i]; best = i; }
-        __syncthreads();
-        const double tb = lo + step * best;
+        for (int m = 64; m < nm; ++m) mx = fmax(mx, fma(static_cast<double>(m), tt, lane_value(lmax1, m - 64)));
+        // arg-min over lanes (ties -> lowest lane)
+        double f = mx - mn;
+        int idx = tid;
+        for (int off = 32; off > 0; off >>= 1) {
+          const double f2 = __shfl_xor(f, off);
+          const int i2 = __shfl_xor(idx, off);
+          if (f2 < f || (f2 == f && i2 < idx)) { f = f2; idx = i2; }
+        }
+        const double tb = lo + step * idx;
         lo = tb - step;
         hi = tb + step;
         t = tb;
@@ -310,12 +178,12 @@ __global__ __launch_bounds__(64) void k_scale(ScaleArgs args) {
 template <FourierType FT>
 hipError_t fwd_dispatch(const FwdArgs& a, int L, dim3 grid, hipStream_t s) {
   switch (L) {
-    case 4: k_forward<4, FT><<<grid, kThreads, 0, s>>>(a); break;
-    case 8: k_forward<8, FT><<<grid, kThreads, 0, s>>>(a); break;
-    case 16: k_forward<16, FT><<<grid, kThreads, 0, s>>>(a); break;
-    case 32: k_forward<32, FT><<<grid, kThreads, 0, s>>>(a); break;
-    case 64: k_forward<64, FT><<<grid, kThreads, 0, s>>>(a); break;
-    case 128: k_forward<128, FT><<<grid, kThreads, 0, s>>>(a); break;
+    case 4: k_forward<4, FT><<<grid, kFftThreads, 0, s>>>(a); break;
+    case 8: k_forward<8, FT><<<grid, kFftThreads, 0, s>>>(a); break;
+    case 16: k_forward<16, FT><<<grid, kFftThreads, 0, s>>>(a); break;
+    case 32: k_forward<32, FT><<<grid, kFftThreads, 0, s>>>(a); break;
+    case 64: k_forward<64, FT><<<grid, kFftThreads, 0, s>>>(a); break;
+    case 128: k_forward<128, FT><<<grid, kFftThreads, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -324,12 +192,12 @@ hipError_t fwd_dispatch(const FwdArgs& a, int L, dim3 grid, hipStream_t s) {
 template <FourierType FT>
 hipError_t inv_dispatch(const InvArgs& a, int L, dim3 grid, hipStream_t s) {
   switch (L) {
-    case 4: k_inverse<4, FT><<<grid, kThreads, 0, s>>>(a); break;
-    case 8: k_inverse<8, FT><<<grid, kThreads, 0, s>>>(a); break;
-    case 16: k_inverse<16, FT><<<grid, kThreads, 0, s>>>(a); break;
-    case 32: k_inverse<32, FT><<<grid, kThreads, 0, s>>>(a); break;
-    case 64: k_inverse<64, FT><<<grid, kThreads, 0, s>>>(a); break;
-    case 128: k_inverse<128, FT><<<grid, kThreads, 0, s>>>(a); break;
+    case 4: k_inverse<4, FT><<<grid, kFftThreads, 0, s>>>(a); break;
+    case 8: k_inverse<8, FT><<<grid, kFftThreads, 0, s>>>(a); break;
+    case 16: k_inverse<16, FT><<<grid, kFftThreads, 0, s>>>(a); break;
+    case 32: k_inverse<32, FT><<<grid, kFftThreads, 0, s>>>(a); break;
+    case 64: k_inverse<64, FT><<<grid, kFftThreads, 0, s>>>(a); break;
+    case 128: k_inverse<128, FT><<<grid, kFftThreads, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

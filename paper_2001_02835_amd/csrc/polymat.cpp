@@ -187,6 +187,7 @@ pm_status enqueue_products(const std::vector<Planned>& items, int prec, hipStrea
       j.nord = it.pr.ntrunc + 1;
       j.L = it.L;
       j.fixed_s = it.pr.scale;
+      j.nser = 1;
     }
     pm_status s = from_hip(timed(PM_PHASE_RESCALE, st, [&] { return launch_scale(sa, st); }));
     if (s) return s;
@@ -442,6 +443,7 @@ pm_status polymat_forward_transform(const void* A, void* At, int n, int ntrunc, 
   sa.jobs[0].nord = ntrunc + 1;
   sa.jobs[0].L = L;
   sa.jobs[0].fixed_s = scale;
+  sa.jobs[0].nser = 1;
   s = from_hip(launch_scale(sa, st));
   if (s) return s;
   FwdArgs fa{};
@@ -472,6 +474,7 @@ pm_status polymat_inverse_transform(const void* Ct, void* C, int n, int ntrunc, 
   sa.jobs[0].nord = ntrunc + 1;
   sa.jobs[0].L = L;
   sa.jobs[0].fixed_s = scale;
+  sa.jobs[0].nser = 1;
   s = from_hip(launch_scale(sa, st));
   if (s) return s;
   InvArgs ia{};
