@@ -87,6 +87,63 @@ def time_steps(torch, pm, items, prec, steps, warmup, ws, timing=False):
     return e0.elapsed_time(e1) / steps, phases
 
 
+def bench_uneven(torch, synth, pm, dev, steps):
+    """64 independent products with N drawn from {64,121,169,225,289} and ntrunc
+    from {15,31,63} (entries N(0,1)*0.7^k), one batched call per step."""
+    shapes = synth.uneven_batch_shapes(synth.rng_for(4, 0), 64)
+    items = []
+    for i, (n, nt) in enumerate(shapes):
+        a = torch.from_numpy(synth.random_series(synth.rng_for(4, 1 + i, 0), n, nt, 0.7)).to(dev)
+        b = torch.from_numpy(synth.random_series(synth.rng_for(4, 1 + i, 1), n, nt, 0.7)).to(dev)
+        items.append(dict(A=a, B=b, C=torch.empty_like(a), scale=0.0))
+    useful = sum(pm.transform_length(nt) * 8.0 * n ** 3 for n, nt in shapes)
+    res = {"workload": "64 products, N in {64,121,169,225,289}, ntrunc in {15,31,63}, entries N(0,1)*0.7^k, "
+                       "one batched call", "useful_gflop_per_batch": round(useful / 1e9, 1)}
+    for prec in ("fp64", "bf16x3"):
+        ws = pm.workspace(pm.batched_workspace_size(items, prec), dev)
+        ms, ph = time_steps(torch, pm, items, prec, steps, 1, ws, timing=True)
+        res[prec] = {"ms_per_batch": round(ms, 3), "mults_per_s": round(64 / (ms * 1e-3), 1),
+                     "useful_tflops": round(useful / (ms * 1e-3) / 1e12, 2),
+                     "phase_ms_per_batch": {k: round(v[0] / steps, 3) for k, v in ph.items() if v[1]}}
+        del ws
+    return res
+
+
+def bench_nspt(torch, synth, pm, dev, steps):
+    """NSPT Euler-Langevin step: 8 replicas x 4 links, SU(225) (L=15, k=4), ntrunc=31,
+    eps=0.01, started at the twisted vacuum and evolved by warm-up steps."""
+    import numpy as np
+    L, k, nt, eps, R = 15, 4, 31, 0.01, 8
+    n = L * L
+    u = torch.from_numpy(synth.vacuum_links(L, k, nt, replicas=R)).to(dev)
+    rng = synth.rng_for(5, 0)
+    noise = [torch.from_numpy(synth.langevin_noise(rng, R, n)).to(dev) for _ in range(2)]
+    prm = pm.nspt_params(L, k, nt, eps)
+    res = {"workload": "8 replicas x 4 links, N=225 (L=15, k=4), ntrunc=31, eps=0.01, FP64 links"}
+    for prec in ("fp64", "bf16x3"):
+        ws = pm.workspace(pm.nspt_workspace_size(R, prm, prec), dev)
+        for i in range(2):
+            pm.nspt_langevin_step(u, noise[i % 2], prm, prec, ws=ws)
+        torch.cuda.synchronize()
+        pm.timing_read()
+        pm.timing_enable(True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(steps):
+            pm.nspt_langevin_step(u, noise[i % 2], prm, prec, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        pm.timing_enable(False)
+        ph = pm.timing_read()
+        ms = e0.elapsed_time(e1) / steps
+        res[prec] = {"ms_per_step": round(ms, 3), "steps_per_s": round(1e3 / ms, 3),
+                     "replica_steps_per_s": round(R * 1e3 / ms, 2),
+                     "phase_ms_per_step": {kk: round(v[0] / steps, 3) for kk, v in ph.items() if v[1]}}
+        del ws
+    return res
+
+
 def cpu_baseline(seconds: float):
     """The FP64 oracle (naive star product, BLAS matmul per term) on the host
     cores, on products of the headline shape until `seconds` have elapsed."""
@@ -123,6 +180,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-extra", action="store_true", help="skip the ntrunc = 63 precision lines")
+    ap.add_argument("--nspt-steps", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args(argv)
@@ -202,6 +260,10 @@ def main(argv=None):
                 extra[prec] = {"error": str(exc)}
         out["ntrunc63"] = {"workload": "1 product N=225 ntrunc=63 (L=128), entries N(0,1)*1.3^k, auto rescale",
                            **extra}
+
+    if not args.no_extra:
+        out["batched_uneven"] = bench_uneven(torch, synth, pm, dev, max(args.steps // 20, 3))
+        out["nspt_step"] = bench_nspt(torch, synth, pm, dev, args.nspt_steps)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

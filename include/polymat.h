@@ -181,8 +181,9 @@ enum {
   PM_PHASE_FORWARD = 1,   /* Steps 1-2: rescale, pad, forward transform */
   PM_PHASE_PRODUCT = 2,   /* Step 3: mode-wise complex matrix products */
   PM_PHASE_INVERSE = 3,   /* Steps 4-5: inverse transform, truncation, unscale */
-  PM_PHASE_OTHER = 4,     /* NSPT element-wise passes */
-  PM_NUM_PHASES = 5
+  PM_PHASE_OTHER = 4,     /* NSPT element-wise passes (trace, force and noise) */
+  PM_PHASE_RETRUNC = 5,   /* NSPT re-truncation of Fourier-space products */
+  PM_NUM_PHASES = 6
 };
 pm_status polymat_timing_enable(int on);
 pm_status polymat_timing_read(double* ms, int* launches);

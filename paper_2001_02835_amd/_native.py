@@ -15,7 +15,7 @@ PM_OK, PM_ERR_INVALID, PM_ERR_WORKSPACE, PM_ERR_DEVICE, PM_ERR_UNSUPPORTED = ran
 PM_PREC_FP64, PM_PREC_FP32, PM_PREC_BF16X3 = range(3)
 PM_OP_N, PM_OP_C = 0, 1
 PM_MAX_NTRUNC = 63
-PHASES = ("rescale", "forward", "product", "inverse", "other")
+PHASES = ("rescale", "forward", "product", "inverse", "other", "retrunc")
 
 
 class PmProblem(ctypes.Structure):

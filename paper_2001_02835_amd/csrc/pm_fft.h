@@ -117,17 +117,12 @@ __device__ __forceinline__ void forward_from_tile(const double2 (*tile)[kEnt], i
 
 // ------------------------------------------------------------ inverse
 
-// acc[k][lane] <- sum_p Ct[p] w^{-kp} for k < nord (no 1/L), where
-// load(p) returns mode p of this thread's entry.  Ends with a barrier, after
-// which every wavefront may read acc.
-template <int L, int R, typename Load>
-__device__ __forceinline__ void inverse_residue(Load&& load, double2 (*acc)[kEnt], int nord, int lane) {
+// acc[k][lane] <- sum_p Ct[p] w^{-kp} for k < nord (no 1/L), from the modes
+// d[q] = Ct[4q + R] of this thread's entry (d is overwritten).  Ends with a
+// barrier, after which every wavefront may read acc.
+template <int L, int R>
+__device__ __forceinline__ void inverse_from_modes(double2* d, double2 (*acc)[kEnt], int nord, int lane) {
   constexpr int M = L / 4;
-  double2 d[M];
-  static_for<0, M>([&](auto qi) {
-    constexpr int q = decltype(qi)::value;
-    d[q] = load(4 * q + R);
-  });
   dft_inplace<M, -1>(d);
   auto term = [&](auto ki) {
     constexpr int k = decltype(ki)::value;
@@ -162,6 +157,18 @@ __device__ __forceinline__ void inverse_residue(Load&& load, double2 (*acc)[kEnt
     });
   }
   __syncthreads();
+}
+
+// Same, where load(p) returns mode p of this thread's entry.
+template <int L, int R, typename Load>
+__device__ __forceinline__ void inverse_residue(Load&& load, double2 (*acc)[kEnt], int nord, int lane) {
+  constexpr int M = L / 4;
+  double2 d[M];
+  static_for<0, M>([&](auto qi) {
+    constexpr int q = decltype(qi)::value;
+    d[q] = load(4 * q + R);
+  });
+  inverse_from_modes<L, R>(d, acc, nord, lane);
 }
 
 template <int L, typename Load>

@@ -96,6 +96,22 @@ hipError_t launch_gemm(const GemmArgs& a, FourierType t, hipStream_t s);
 int gemm_tile_bf16();
 hipError_t launch_gemm_bf16(const GemmArgs& a, hipStream_t s);
 
+// Phase timing (polymat.cpp): when enabled, each launch is bracketed by two
+// HIP events on its stream.
+struct PhaseMark {
+  int phase;
+  hipEvent_t a;
+};
+PhaseMark phase_begin(int phase, hipStream_t s);
+void phase_end(const PhaseMark& m, hipStream_t s);
+template <typename F>
+hipError_t timed(int phase, hipStream_t s, F&& launch) {
+  PhaseMark m = phase_begin(phase, s);
+  hipError_t e = launch();
+  phase_end(m, s);
+  return e;
+}
+
 // Leading dimension (elements) of one BF16 plane row for matrix size n.
 __host__ __device__ inline int bf16_ld(int n) { return (n + 7) / 8 * 8; }
 

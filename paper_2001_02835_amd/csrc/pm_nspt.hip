@@ -135,7 +135,7 @@ struct GemmBatch {
   }
   void flush() {
     if (status || a.njobs == 0) return;
-    status = st(launch_gemm(a, ft, s));
+    status = st(timed(PM_PHASE_PRODUCT, s, [&] { return launch_gemm(a, ft, s); }));
     a.njobs = 0;
     a.total_tiles = 0;
   }
@@ -162,7 +162,7 @@ struct RetruncBatch {
   }
   void flush() {
     if (status || a.njobs == 0) return;
-    status = st(launch_retrunc(a, l->L, l->E, fin, fout, s));
+    status = st(timed(PM_PHASE_RETRUNC, s, [&] { return launch_retrunc(a, l->L, l->E, fin, fout, s); }));
     a.njobs = 0;
   }
 };
@@ -234,7 +234,7 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
     for (int r = 0; r < R; ++r)
       for (int mu = 0; mu < 4; ++mu) {
         if (na.njobs == kMaxTransformJobs) {
-          pm_status e = st(launch_norms(na, nord, s));
+          pm_status e = st(timed(PM_PHASE_RESCALE, s, [&] { return launch_norms(na, nord, s); }));
           if (e) return e;
           na.njobs = 0;
         }
@@ -244,7 +244,7 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
         j.E = E;
         j.nord = nord;
       }
-    pm_status e = st(launch_norms(na, nord, s));
+    pm_status e = st(timed(PM_PHASE_RESCALE, s, [&] { return launch_norms(na, nord, s); }));
     if (e) return e;
     ScaleArgs sa{};
     sa.njobs = 2;
@@ -259,7 +259,7 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
     sa.jobs[1].rec = unit;
     sa.jobs[1].fixed_s = 1.0;
     sa.jobs[1].nser = 1;
-    e = st(launch_scale(sa, s));
+    e = st(timed(PM_PHASE_RESCALE, s, [&] { return launch_scale(sa, s); }));
     if (e) return e;
   }
 
@@ -269,7 +269,7 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
     for (int r = 0; r < R; ++r)
       for (int mu = 0; mu < 4; ++mu) {
         if (fa.njobs == kMaxTransformJobs) {
-          pm_status e = st(launch_forward(fa, L, E, fin, s));
+          pm_status e = st(timed(PM_PHASE_FORWARD, s, [&] { return launch_forward(fa, L, E, fin, s); }));
           if (e) return e;
           fa.njobs = 0;
         }
@@ -281,7 +281,7 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
         j.nord = nord;
         j.n = n;
       }
-    pm_status e = st(launch_forward(fa, L, E, fin, s));
+    pm_status e = st(timed(PM_PHASE_FORWARD, s, [&] { return launch_forward(fa, L, E, fin, s); }));
     if (e) return e;
   }
 
@@ -336,7 +336,7 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
     CombineArgs ca{};
     auto flush = [&]() -> pm_status {
       if (ca.njobs == 0) return PM_OK;
-      pm_status e = st(launch_inv_combine(ca, L, E, fout, s));
+      pm_status e = st(timed(PM_PHASE_INVERSE, s, [&] { return launch_inv_combine(ca, L, E, fout, s); }));
       ca.njobs = 0;
       return e;
     };
@@ -375,7 +375,7 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
     for (int r = 0; r < R; ++r)
       for (int m = 0; m < 4; ++m) {
         if (ta.njobs == kMaxTransformJobs) {
-          pm_status e = st(launch_trace(ta, nord, s));
+          pm_status e = st(timed(PM_PHASE_OTHER, s, [&] { return launch_trace(ta, nord, s); }));
           if (e) return e;
           ta.njobs = 0;
         }
@@ -385,7 +385,7 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
         j.n = n;
         j.nord = nord;
       }
-    pm_status e = st(launch_trace(ta, nord, s));
+    pm_status e = st(timed(PM_PHASE_OTHER, s, [&] { return launch_trace(ta, nord, s); }));
     if (e) return e;
     ForceArgs fa{};
     fa.eps = p->eps;
@@ -393,7 +393,7 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
     for (int r = 0; r < R; ++r)
       for (int m = 0; m < 4; ++m) {
         if (fa.njobs == kMaxForceJobs) {
-          e = st(launch_force(fa, n, nord, s));
+          e = st(timed(PM_PHASE_OTHER, s, [&] { return launch_force(fa, n, nord, s); }));
           if (e) return e;
           fa.njobs = 0;
         }
@@ -406,14 +406,14 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
         j.n = n;
         j.nord = nord;
       }
-    e = st(launch_force(fa, n, nord, s));
+    e = st(timed(PM_PHASE_OTHER, s, [&] { return launch_force(fa, n, nord, s); }));
     if (e) return e;
     // Fourier coefficients of Y (already scaled: unit record)
     FwdArgs fw{};
     for (int r = 0; r < R; ++r)
       for (int m = 0; m < 4; ++m) {
         if (fw.njobs == kMaxTransformJobs) {
-          e = st(launch_forward(fw, L, E, fin, s));
+          e = st(timed(PM_PHASE_FORWARD, s, [&] { return launch_forward(fw, L, E, fin, s); }));
           if (e) return e;
           fw.njobs = 0;
         }
@@ -425,7 +425,7 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
         j.nord = nord;
         j.n = n;
       }
-    e = st(launch_forward(fw, L, E, fin, s));
+    e = st(timed(PM_PHASE_FORWARD, s, [&] { return launch_forward(fw, L, E, fin, s); }));
     if (e) return e;
   }
 
@@ -488,7 +488,7 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
     for (int r = 0; r < R; ++r)
       for (int m = 0; m < 4; ++m) {
         if (ca.njobs == kMaxCombineJobs) {
-          pm_status e = st(launch_inv_combine(ca, L, E, fout, s));
+          pm_status e = st(timed(PM_PHASE_INVERSE, s, [&] { return launch_inv_combine(ca, L, E, fout, s); }));
           if (e) return e;
           ca.njobs = 0;
         }
@@ -502,7 +502,7 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
         j.nord = nord;
         j.kmin = 1;
       }
-    pm_status e = st(launch_inv_combine(ca, L, E, fout, s));
+    pm_status e = st(timed(PM_PHASE_INVERSE, s, [&] { return launch_inv_combine(ca, L, E, fout, s); }));
     if (e) return e;
   }
   return PM_OK;

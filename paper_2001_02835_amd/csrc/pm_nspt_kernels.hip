@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kFftThreads) void k_retrunc(RetruncArgs args) {
 
 // --------------------------------------------- inverse of a weighted sum
 
-template <int L, FourierType FIN>
+template <int L, FourierType FIN, int NSRC>
 __global__ __launch_bounds__(kFftThreads) void k_inv_combine(CombineArgs args) {
   __shared__ double2 acc[L / 2][kEnt];
   const CombineJob& jb = args.jobs[blockIdx.y];
@@ -73,13 +73,30 @@ __global__ __launch_bounds__(kFftThreads) void k_inv_combine(CombineArgs args) {
   const int r = threadIdx.x / kWave;
   const int e = e0 + lane;
   const bool valid = e < E;
-  auto load = [&](int p) {
-    double2 v = make_double2(0.0, 0.0);
-    if (valid)
-      for (int q = 0; q < jb.nsrc; ++q) v = cadd(v, cmul(jb.coef[q], load_mode<FIN>(jb.src[q], E, p, e)));
-    return v;
+  const int ec = valid ? e : 0;        // clamped entry: loads stay in bounds, the result is not stored
+  constexpr int M = L / 4;
+  // modes 4q + r of sum_src coef * src, one source at a time (bounded registers)
+  auto build = [&](auto rc) {
+    constexpr int R = decltype(rc)::value;
+    double2 d[M];
+    static_for<0, M>([&](auto qi) { d[decltype(qi)::value] = make_double2(0.0, 0.0); });
+#pragma unroll 1
+    for (int q = 0; q < NSRC; ++q) {
+      const void* src = jb.src[q];
+      const double2 c = jb.coef[q];
+      static_for<0, M>([&](auto qi) {
+        constexpr int m = decltype(qi)::value;
+        d[m] = cadd(d[m], cmul(c, load_mode<FIN>(src, E, 4 * m + R, ec)));
+      });
+    }
+    inverse_from_modes<L, R>(d, acc, jb.nord, lane);
   };
-  inverse_to_lds<L>(load, acc, jb.nord, lane, r);
+  switch (r) {
+    case 0: build(std::integral_constant<int, 0>{}); break;
+    case 1: build(std::integral_constant<int, 1>{}); break;
+    case 2: build(std::integral_constant<int, 2>{}); break;
+    default: build(std::integral_constant<int, 3>{}); break;
+  }
   if (valid)
     for (int k = r; k < jb.nord; k += 4)
       if (k >= jb.kmin) jb.dst[static_cast<size_t>(k) * E + e] = cscale(acc[k][lane], jb.rec->sinv[k]);
@@ -167,15 +184,15 @@ hipError_t retrunc_dispatch(const RetruncArgs& a, int L, dim3 g, hipStream_t s) 
   return hipGetLastError();
 }
 
-template <FourierType FIN>
+template <FourierType FIN, int NSRC>
 hipError_t combine_dispatch(const CombineArgs& a, int L, dim3 g, hipStream_t s) {
   switch (L) {
-    case 4: k_inv_combine<4, FIN><<<g, kFftThreads, 0, s>>>(a); break;
-    case 8: k_inv_combine<8, FIN><<<g, kFftThreads, 0, s>>>(a); break;
-    case 16: k_inv_combine<16, FIN><<<g, kFftThreads, 0, s>>>(a); break;
-    case 32: k_inv_combine<32, FIN><<<g, kFftThreads, 0, s>>>(a); break;
-    case 64: k_inv_combine<64, FIN><<<g, kFftThreads, 0, s>>>(a); break;
-    case 128: k_inv_combine<128, FIN><<<g, kFftThreads, 0, s>>>(a); break;
+    case 4: k_inv_combine<4, FIN, NSRC><<<g, kFftThreads, 0, s>>>(a); break;
+    case 8: k_inv_combine<8, FIN, NSRC><<<g, kFftThreads, 0, s>>>(a); break;
+    case 16: k_inv_combine<16, FIN, NSRC><<<g, kFftThreads, 0, s>>>(a); break;
+    case 32: k_inv_combine<32, FIN, NSRC><<<g, kFftThreads, 0, s>>>(a); break;
+    case 64: k_inv_combine<64, FIN, NSRC><<<g, kFftThreads, 0, s>>>(a); break;
+    case 128: k_inv_combine<128, FIN, NSRC><<<g, kFftThreads, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -195,8 +212,14 @@ hipError_t launch_retrunc(const RetruncArgs& a, int L, int max_entries, FourierT
 hipError_t launch_inv_combine(const CombineArgs& a, int L, int max_entries, FourierType fin, hipStream_t s) {
   if (a.njobs <= 0) return hipSuccess;
   dim3 g((max_entries + kEnt - 1) / kEnt, a.njobs);
-  if (fin == kF64) return combine_dispatch<kF64>(a, L, g, s);
-  return combine_dispatch<kF32>(a, L, g, s);
+  // every job of one launch has the same number of sources (1 or kMaxCombine)
+  const int ns = a.jobs[0].nsrc;
+  for (int j = 1; j < a.njobs; ++j)
+    if (a.jobs[j].nsrc != ns) return hipErrorInvalidValue;
+  if (ns == 1) return fin == kF64 ? combine_dispatch<kF64, 1>(a, L, g, s) : combine_dispatch<kF32, 1>(a, L, g, s);
+  if (ns == kMaxCombine)
+    return fin == kF64 ? combine_dispatch<kF64, kMaxCombine>(a, L, g, s) : combine_dispatch<kF32, kMaxCombine>(a, L, g, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_trace(const TraceArgs& a, int max_nord, hipStream_t s) {

@@ -154,13 +154,17 @@ __global__ __launch_bounds__(64) void k_scale(ScaleArgs args) {
           mn = fmin(mn, fma(static_cast<double>(m), tt, y));
         }
         for (int m = 64; m < nm; ++m) mx = fmax(mx, fma(static_cast<double>(m), tt, lane_value(lmax1, m - 64)));
-        // arg-min over lanes (ties -> lowest lane)
+        // arg-min over lanes; near-ties (a flat objective, e.g. only one
+        // nonzero order) go to the candidate closest to t = 0 (s = 1)
         double f = mx - mn;
         int idx = tid;
         for (int off = 32; off > 0; off >>= 1) {
           const double f2 = __shfl_xor(f, off);
           const int i2 = __shfl_xor(idx, off);
-          if (f2 < f || (f2 == f && i2 < idx)) { f = f2; idx = i2; }
+          const double tol = 1e-9 * fmax(1.0, fabs(f));
+          const double t1 = fabs(lo + step * idx), t2 = fabs(lo + step * i2);
+          const bool better = (f2 < f - tol) || (fabs(f2 - f) <= tol && (t2 < t1 || (t2 == t1 && i2 < idx)));
+          if (better) { f = f2; idx = i2; }
         }
         const double tb = lo + step * idx;
         lo = tb - step;

@@ -117,20 +117,6 @@ hipEvent_t pooled_event() {
   return e;
 }
 
-// Run `launch` (a callable returning hipError_t), bracketed by events when
-// timing is enabled.
-template <typename F>
-hipError_t timed(int phase, hipStream_t st, F&& launch) {
-  if (!g_timing.load(std::memory_order_relaxed)) return launch();
-  std::lock_guard<std::mutex> lk(g_tmu);
-  hipEvent_t a = pooled_event(), b = pooled_event();
-  if (a) (void)hipEventRecord(a, st);
-  hipError_t e = launch();
-  if (b) (void)hipEventRecord(b, st);
-  if (a && b) g_recs.push_back(TimingRec{phase, a, b});
-  return e;
-}
-
 // Enqueue the whole FFT-CONV pipeline for a list of validated problems whose
 // workspace regions are given.
 struct Planned {
@@ -313,6 +299,31 @@ pm_status plan_batch(const pm_problem* problems, int count, int prec, char* ws, 
 }
 
 }  // namespace
+
+namespace pm {
+
+PhaseMark phase_begin(int phase, hipStream_t st) {
+  PhaseMark m{phase, nullptr};
+  if (!g_timing.load(std::memory_order_relaxed)) return m;
+  std::lock_guard<std::mutex> lk(g_tmu);
+  m.a = pooled_event();
+  if (m.a) (void)hipEventRecord(m.a, st);
+  return m;
+}
+
+void phase_end(const PhaseMark& m, hipStream_t st) {
+  if (!m.a) return;
+  std::lock_guard<std::mutex> lk(g_tmu);
+  hipEvent_t b = pooled_event();
+  if (!b) {
+    g_pool.push_back(m.a);
+    return;
+  }
+  (void)hipEventRecord(b, st);
+  g_recs.push_back(TimingRec{m.phase, m.a, b});
+}
+
+}  // namespace pm
 
 extern "C" {
 
