@@ -1,0 +1,116 @@
+"""Tile-shape autotuner for the mode-wise product kernels.
+
+Run on an MI355X after building the library:
+
+    python -m paper_2001_02835_amd.autotune [--out table.h] [--sizes 64,121,169,225,289]
+
+For every compiled tile configuration (forced with POLYMAT_GEMM_CONFIG in a
+child process) it times the product phase of a batch of 4 products with
+ntrunc = 31 for each matrix size and precision, checks the result against a
+direct FP64 evaluation of one product, and writes a C header with the fastest
+configuration per size interval.  The committed csrc/pm_gemm_tuning.h was
+produced this way.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+NUM_CONFIGS = 10
+
+
+def measure(sizes, steps=20):
+    """Child process: time the product phase for every size (current config)."""
+    import numpy as np
+    import torch
+    sys.path.insert(0, ROOT)
+    import synth
+    import paper_2001_02835_amd as pm
+    dev = "cuda:0"
+    out = {}
+    for n in sizes:
+        nt = 31
+        items = []
+        for i in range(4):
+            a = torch.from_numpy(synth.random_series(synth.rng_for(2, i, 0), n, nt, 0.5)).to(dev)
+            b = torch.from_numpy(synth.random_series(synth.rng_for(2, i, 1), n, nt, 0.5)).to(dev)
+            items.append(dict(A=a, B=b, C=torch.empty_like(a)))
+        # correctness of the configuration: one mode-wise product against a
+        # direct evaluation (the series product at ntrunc = 0 is A0 B0)
+        a0 = synth.random_series(synth.rng_for(3, n, 0), n, 0)
+        b0 = synth.random_series(synth.rng_for(3, n, 1), n, 0)
+        for prec in ("fp64", "fp32"):
+            c0 = pm.polymat_mul(torch.from_numpy(a0).to(dev), torch.from_numpy(b0).to(dev), precision=prec)
+            ref = a0[0] @ b0[0]
+            err = float(np.abs(c0.cpu().numpy()[0] - ref).max() / np.abs(ref).max())
+            if err > (1e-12 if prec == "fp64" else 1e-5):
+                raise SystemExit(f"config gives wrong products ({prec}, n={n}, err={err})")
+            ws = pm.workspace(pm.batched_workspace_size(items, prec), dev)
+            for _ in range(3):
+                pm.polymat_mul_batched(items, prec, ws=ws)
+            torch.cuda.synchronize()
+            pm.timing_read()
+            pm.timing_enable(True)
+            for _ in range(steps):
+                pm.polymat_mul_batched(items, prec, ws=ws)
+            torch.cuda.synchronize()
+            pm.timing_enable(False)
+            out[f"{prec}:{n}"] = pm.timing_read()["product"][0] / steps
+            del ws
+    print(json.dumps(out))
+
+
+def header(table) -> str:
+    lines = ["// Tile configuration per matrix size for the mode-wise products, measured",
+             "// on MI355X by paper_2001_02835_amd/autotune.py (fastest of the compiled",
+             "// shapes for a batch of 4 products, ntrunc = 31).  {n_max, config}: the first",
+             "// row with n <= n_max applies.",
+             "#pragma once", "", "namespace pm {", "", "struct TuneRow { int n_max, cfg; };"]
+    for prec, rows in table.items():
+        body = ", ".join(f"{{{m}, {c}}}" for m, c in rows)
+        lines.append(f"constexpr TuneRow kTune_{prec}[] = {{{body}}};")
+    lines += ["", "}  // namespace pm", ""]
+    return "\n".join(lines)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sizes", default="64,121,169,225,289")
+    ap.add_argument("--out", default=os.path.join(HERE, "csrc", "pm_gemm_tuning.h"))
+    ap.add_argument("--child", action="store_true")
+    a = ap.parse_args(argv)
+    sizes = [int(x) for x in a.sizes.split(",")]
+    if a.child:
+        measure(sizes)
+        return 0
+    results = {}
+    for cfg in range(NUM_CONFIGS):
+        env = dict(os.environ, POLYMAT_GEMM_CONFIG=str(cfg))
+        r = subprocess.run([sys.executable, "-m", "paper_2001_02835_amd.autotune", "--child", "--sizes", a.sizes],
+                           env=env, capture_output=True, text=True, cwd=ROOT, timeout=600)
+        if r.returncode != 0:
+            print(f"config {cfg}: failed\n{r.stderr[-2000:]}", file=sys.stderr)
+            continue
+        results[cfg] = json.loads(r.stdout.strip().splitlines()[-1])
+        print(f"config {cfg}: {results[cfg]}", flush=True)
+    table = {}
+    for prec in ("fp64", "fp32"):
+        rows = []
+        for i, n in enumerate(sizes):
+            best = min(results, key=lambda c: results[c][f"{prec}:{n}"])
+            n_max = (n + sizes[i + 1]) // 2 if i + 1 < len(sizes) else 1 << 30
+            rows.append((n_max, best))
+        table[prec] = rows
+    with open(a.out, "w") as f:
+        f.write(header(table))
+    print(f"wrote {a.out}")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

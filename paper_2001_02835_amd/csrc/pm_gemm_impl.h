@@ -1,0 +1,550 @@
+#pragma once
+// Mode-wise complex matrix products (FFT-CONV Step 3, eq. (8)) on MFMA:
+// the kernel template shared by the FP64 and FP32 instantiations.
+//
+// For every product job and every mode p < L:
+//     Ct^(p) = opA(At)^(p) * opB(Bt)^(p)
+// where a plain operand X reads mode p of its transform and a conjugated
+// operand (the series X^+) reads mode (L - p) mod L conjugate-transposed:
+// the transform of X^+ at mode p is (Xt^(-p))^+, so X^+ costs no extra pass.
+//
+// Coefficients are interleaved complex (re, im) in FP64 or FP32, unpadded
+// N x N row-major per mode.  A complex product is four real MFMA products
+// (re*re - im*im, re*im + im*re).  One work-group computes a BM x BN tile of
+// one mode with WGM x WGN wavefronts of WM x WN 16x16 blocks each; K is
+// staged through double-buffered LDS in chunks of 16.  Ragged edges are
+// zero-filled on load; whole 16x16 blocks and whole k-steps of 4 that lie
+// outside the matrix are skipped.  Logical tile ids are remapped so that the
+// tiles of one mode run on one XCD and share its L2.
+#include "pm_common.h"
+#include "pm_kernels.h"
+
+#include <cstdlib>
+
+namespace pm {
+
+namespace gemm_detail {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Cx;
+template <> struct Cx<double> {
+  using T2 = double2;
+  using Acc = d4;
+  static constexpr int kPad = 1;   // LDS row pad (elements): 65 * 16 B = 4 banks shift
+  __device__ static __forceinline__ Acc mfma(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // output element v of lane l sits at row 4 v + l / 16, column l % 16
+  __device__ static __forceinline__ int out_row(int lane, int v) { return 4 * v + lane / 16; }
+};
+template <> struct Cx<float> {
+  using T2 = float2;
+  using Acc = f4;
+  static constexpr int kPad = 2;
+  __device__ static __forceinline__ Acc mfma(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // output element v of lane l sits at row 4 (l / 16) + v, column l % 16
+  __device__ static __forceinline__ int out_row(int lane, int v) { return 4 * (lane / 16) + v; }
+};
+
+template <typename T2> __device__ __forceinline__ T2 zero2() { T2 z; z.x = 0; z.y = 0; return z; }
+template <typename T2> __device__ __forceinline__ T2 conj2(T2 v) { v.y = -v.y; return v; }
+
+template <typename T, int WM, int WN, int WGM, int WGN>
+struct GemmCfg {
+  static constexpr int BM = 16 * WM * WGM;
+  static constexpr int BN = 16 * WN * WGN;
+  static constexpr int BK = 16;
+  static constexpr int NT = kWave * WGM * WGN;
+  static constexpr int LA = (BM * BK) / NT;    // A elements loaded per thread per chunk
+  static constexpr int LB = (BK * BN) / NT;
+  static_assert((BM * BK) % NT == 0 && (BK * BN) % NT == 0, "tile/thread mismatch");
+};
+
+// Uniform (SGPR) copy of a wave-uniform predicate, so the compiler branches on
+// the scalar unit instead of masking lanes.
+__device__ __forceinline__ bool uniform(bool b) { return __builtin_amdgcn_readfirstlane(b ? 1 : 0) != 0; }
+
+// G3 selects the three-product form of the complex multiply-accumulate
+// (Gauss): P1 += Xr Yr, P2 += Xi Yi, P3 += (Xr + Xi)(Yr + Yi), then
+// Re = P1 - P2, Im = P3 - P1 - P2.  It issues 3 MFMAs per k-step and block
+// instead of 4; the sums Xr + Xi and Yr + Yi are formed in registers from the
+// staged fragments, so memory traffic is unchanged.
+template <typename T, int WM, int WN, int WGM, int WGN, bool OPA, bool OPB, bool G3>
+__global__ __launch_bounds__(kWave * WGM * WGN) void k_cgemm(GemmArgs args) {
+  using C = Cx<T>;
+  using T2 = typename C::T2;
+  using Acc = typename C::Acc;
+  using G = GemmCfg<T, WM, WN, WGM, WGN>;
+  constexpr int BM = G::BM, BN = G::BN, BK = G::BK, NT = G::NT;
+  constexpr int PAD = C::kPad;
+
+  __shared__ T2 As[2][BK][BM + PAD];
+  __shared__ T2 Bs[2][BK][BN + PAD];
+
+  // ---- which job, mode and tile
+  const int id = xcd_remap(blockIdx.x, gridDim.x);
+  int jidx = 0;
+  for (int j = 1; j < args.njobs; ++j)
+    if (id >= args.jobs[j].tile_begin) jidx = j;
+  const GemmJob& jb = args.jobs[jidx];
+  const int local = id - jb.tile_begin;
+  const int per_mode = jb.tiles_m * jb.tiles_n;
+  const int p = local / per_mode;
+  const int rem = local - p * per_mode;
+  const int tm = rem / jb.tiles_n;
+  const int tn = rem - tm * jb.tiles_n;
+  const int n = jb.n, L = jb.L;
+  const size_t E = static_cast<size_t>(n) * n;
+  const int pa = OPA ? (L - p) % L : p;
+  const int pb = OPB ? (L - p) % L : p;
+  const T2* __restrict__ Ag = reinterpret_cast<const T2*>(jb.A) + pa * E;
+  const T2* __restrict__ Bg = reinterpret_cast<const T2*>(jb.B) + pb * E;
+  T2* __restrict__ Cg = reinterpret_cast<T2*>(jb.C) + static_cast<size_t>(p) * E;
+  const int row0 = tm * BM, col0 = tn * BN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  const int wr = wave / WGN, wc = wave - (wave / WGN) * WGN;
+  const int wrow0 = wr * 16 * WM, wcol0 = wc * 16 * WN;
+  const int li = lane & 15, lk = lane >> 4;
+
+  // ---- per-thread staging coordinates (fixed over the K loop)
+  // A element (i, k): plain -> Ag[i][k] (coalesced along k); conjugated ->
+  // conj(Ag[k][i]) (coalesced along i).  Same idea for B with (k, j).
+  int a_i[G::LA], a_k[G::LA], b_j[G::LB], b_k[G::LB];
+#pragma unroll
+  for (int u = 0; u < G::LA; ++u) {
+    const int q = tid + NT * u;
+    if (!OPA) { a_k[u] = q % BK; a_i[u] = q / BK; } else { a_i[u] = q % BM; a_k[u] = q / BM; }
+  }
+#pragma unroll
+  for (int u = 0; u < G::LB; ++u) {
+    const int q = tid + NT * u;
+    if (!OPB) { b_j[u] = q % BN; b_k[u] = q / BN; } else { b_k[u] = q % BK; b_j[u] = q / BK; }
+  }
+
+  T2 ra[G::LA], rb[G::LB];
+  bool oka[G::LA], okb[G::LB];
+  // Branch-free loads: out-of-range elements read a clamped in-range address;
+  // they are replaced by zero only when written to LDS, so that the loads of
+  // the next chunk stay in flight while the current chunk is multiplied.
+  auto load_chunk = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < G::LA; ++u) {
+      const int gi = row0 + a_i[u], gk = k0 + a_k[u];
+      const bool ok = gi < n && gk < n;
+      const int ci = ok ? gi : 0, ck = ok ? gk : 0;
+      ra[u] = OPA ? Ag[static_cast<size_t>(ck) * n + ci] : Ag[static_cast<size_t>(ci) * n + ck];
+      oka[u] = ok;
+    }
+#pragma unroll
+    for (int u = 0; u < G::LB; ++u) {
+      const int gj = col0 + b_j[u], gk = k0 + b_k[u];
+      const bool ok = gj < n && gk < n;
+      const int cj = ok ? gj : 0, ck = ok ? gk : 0;
+      rb[u] = OPB ? Bg[static_cast<size_t>(cj) * n + ck] : Bg[static_cast<size_t>(ck) * n + cj];
+      okb[u] = ok;
+    }
+  };
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < G::LA; ++u) {
+      T2 v;
+      v.x = oka[u] ? ra[u].x : T(0);
+      v.y = oka[u] ? (OPA ? -ra[u].y : ra[u].y) : T(0);
+      As[buf][a_k[u]][a_i[u]] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < G::LB; ++u) {
+      T2 v;
+      v.x = okb[u] ? rb[u].x : T(0);
+      v.y = okb[u] ? (OPB ? -rb[u].y : rb[u].y) : T(0);
+      Bs[buf][b_k[u]][b_j[u]] = v;
+    }
+  };
+
+  // 4-product form: cr, ci.  3-product form: cr = P1, ci = P2, c3 = P3.
+  Acc cr[WM][WN], ci[WM][WN], c3[G3 ? WM : 1][G3 ? WN : 1];
+#pragma unroll
+  for (int a = 0; a < WM; ++a)
+#pragma unroll
+    for (int b = 0; b < WN; ++b) { cr[a][b] = Acc{0, 0, 0, 0}; ci[a][b] = Acc{0, 0, 0, 0}; }
+  if constexpr (G3) {
+#pragma unroll
+    for (int a = 0; a < WM; ++a)
+#pragma unroll
+      for (int b = 0; b < WN; ++b) c3[a][b] = Acc{0, 0, 0, 0};
+  }
+
+  // wave-uniform activity of each 16x16 block (blocks fully outside the matrix are skipped)
+  bool act[WM][WN];
+#pragma unroll
+  for (int a = 0; a < WM; ++a)
+#pragma unroll
+    for (int b = 0; b < WN; ++b)
+      act[a][b] = uniform(row0 + wrow0 + 16 * a < n && col0 + wcol0 + 16 * b < n);
+
+  auto mma_step = [&](int buf, int s) {
+    const int kk = 4 * s + lk;
+    T2 fa[WM], fb[WN];
+#pragma unroll
+    for (int a = 0; a < WM; ++a) fa[a] = As[buf][kk][wrow0 + 16 * a + li];
+#pragma unroll
+    for (int b = 0; b < WN; ++b) fb[b] = Bs[buf][kk][wcol0 + 16 * b + li];
+    if constexpr (G3) {
+      T sa[WM], sb[WN];
+#pragma unroll
+      for (int a = 0; a < WM; ++a) sa[a] = fa[a].x + fa[a].y;
+#pragma unroll
+      for (int b = 0; b < WN; ++b) sb[b] = fb[b].x + fb[b].y;
+#pragma unroll
+      for (int a = 0; a < WM; ++a) {
+#pragma unroll
+        for (int b = 0; b < WN; ++b) {
+          if (act[a][b]) {
+            cr[a][b] = C::mfma(fa[a].x, fb[b].x, cr[a][b]);
+            ci[a][b] = C::mfma(fa[a].y, fb[b].y, ci[a][b]);
+            c3[a][b] = C::mfma(sa[a], sb[b], c3[a][b]);
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < WM; ++a) {
+        const T nai = -fa[a].y;
+#pragma unroll
+        for (int b = 0; b < WN; ++b) {
+          if (act[a][b]) {
+            cr[a][b] = C::mfma(fa[a].x, fb[b].x, cr[a][b]);
+            ci[a][b] = C::mfma(fa[a].x, fb[b].y, ci[a][b]);
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < WN; ++b) {
+          if (act[a][b]) {
+            cr[a][b] = C::mfma(nai, fb[b].y, cr[a][b]);
+            ci[a][b] = C::mfma(fa[a].y, fb[b].x, ci[a][b]);
+          }
+        }
+      }
+    }
+  };
+
+  const int nchunks = (n + BK - 1) / BK;
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    const int buf = c & 1;
+    const int k0 = c * BK;
+    if (c + 1 < nchunks) load_chunk(k0 + BK);
+#pragma unroll
+    for (int s = 0; s < BK / 4; ++s)
+      if (k0 + 4 * s < n) mma_step(buf, s);
+    if (c + 1 < nchunks) store_chunk(buf ^ 1);
+    __syncthreads();
+  }
+
+  // ---- epilogue: interleave re/im and store the tile
+#pragma unroll
+  for (int a = 0; a < WM; ++a) {
+#pragma unroll
+    for (int b = 0; b < WN; ++b) {
+      const int gj = col0 + wcol0 + 16 * b + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = row0 + wrow0 + 16 * a + C::out_row(lane, v);
+        if (gi < n && gj < n) {
+          T2 o;
+          if constexpr (G3) {
+            o.x = cr[a][b][v] - ci[a][b][v];
+            o.y = c3[a][b][v] - cr[a][b][v] - ci[a][b][v];
+          } else {
+            o.x = cr[a][b][v];
+            o.y = ci[a][b][v];
+          }
+          Cg[static_cast<size_t>(gi) * n + gj] = o;
+        }
+      }
+    }
+  }
+}
+
+
+// Second form of the kernel: both operand tiles keep their natural row-major
+// layout in LDS (A as [i][k], B as [k][j], rows padded by one element so that
+// staging stores and fragment reads are free of bank conflicts), and the k
+// index is permuted across the lane groups of the MFMA: in k-step s of a
+// chunk, lane group g (lanes 16g..16g+15) contracts over k = 4g + s.  The
+// MFMA only needs A and B to agree on that assignment.  In full chunks the
+// fragments of two k-steps are read at once (the next two while the current
+// ones are multiplied) and each accumulator receives its two updates back to
+// back, which keeps the FP64 MFMA pipe busier than alternating accumulators.
+template <typename T, int WM, int WN, int WGM, int WGN>
+struct Tile2 {
+  using T2 = typename Cx<T>::T2;
+  using G = GemmCfg<T, WM, WN, WGM, WGN>;
+  static constexpr int BM = G::BM, BN = G::BN, BK = G::BK;
+  static constexpr int kAElems = 2 * BM * (BK + 1);
+  static constexpr int kBElems = 2 * BK * (BN + 1);
+  static constexpr size_t kLdsBytes = sizeof(T2) * (kAElems + kBElems);
+};
+
+template <typename T, int WM, int WN, int WGM, int WGN, bool OPA, bool OPB, bool G3>
+__device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, int tn, char* smem) {
+  using C = Cx<T>;
+  using T2 = typename C::T2;
+  using Acc = typename C::Acc;
+  using G = GemmCfg<T, WM, WN, WGM, WGN>;
+  constexpr int BM = G::BM, BN = G::BN, BK = G::BK, NT = G::NT;
+  typedef T2 ATile[BM][BK + 1];
+  typedef T2 BTile[BK][BN + 1];
+  ATile* As = reinterpret_cast<ATile*>(smem);
+  BTile* Bs = reinterpret_cast<BTile*>(smem + sizeof(T2) * 2 * BM * (BK + 1));
+
+  const int n = jb.n, L = jb.L;
+  const size_t E = static_cast<size_t>(n) * n;
+  const int pa = OPA ? (L - p) % L : p;
+  const int pb = OPB ? (L - p) % L : p;
+  const T2* __restrict__ Ag = reinterpret_cast<const T2*>(jb.A) + pa * E;
+  const T2* __restrict__ Bg = reinterpret_cast<const T2*>(jb.B) + pb * E;
+  T2* __restrict__ Cg = reinterpret_cast<T2*>(jb.C) + static_cast<size_t>(p) * E;
+  const int row0 = tm * BM, col0 = tn * BN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  const int wr = wave / WGN, wc = wave - (wave / WGN) * WGN;
+  const int wrow0 = wr * 16 * WM, wcol0 = wc * 16 * WN;
+  const int li = lane & 15, lg = lane >> 4;
+
+  // staging coordinates: tile element (i, kk) of A and (kk, j) of B
+  int a_i[G::LA], a_k[G::LA], b_j[G::LB], b_k[G::LB];
+#pragma unroll
+  for (int u = 0; u < G::LA; ++u) {
+    const int q = tid + NT * u;
+    if (!OPA) { a_k[u] = q % BK; a_i[u] = q / BK; } else { a_i[u] = q % BM; a_k[u] = q / BM; }
+  }
+#pragma unroll
+  for (int u = 0; u < G::LB; ++u) {
+    const int q = tid + NT * u;
+    if (!OPB) { b_j[u] = q % BN; b_k[u] = q / BN; } else { b_k[u] = q % BK; b_j[u] = q / BK; }
+  }
+
+  T2 ra[G::LA], rb[G::LB];
+  bool oka[G::LA], okb[G::LB];
+  auto load_chunk = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < G::LA; ++u) {
+      const int gi = row0 + a_i[u], gk = k0 + a_k[u];
+      const bool ok = gi < n && gk < n;
+      const int off = ok ? (OPA ? gk * n + gi : gi * n + gk) : 0;
+      ra[u] = Ag[off];
+      oka[u] = ok;
+    }
+#pragma unroll
+    for (int u = 0; u < G::LB; ++u) {
+      const int gj = col0 + b_j[u], gk = k0 + b_k[u];
+      const bool ok = gj < n && gk < n;
+      const int off = ok ? (OPB ? gj * n + gk : gk * n + gj) : 0;
+      rb[u] = Bg[off];
+      okb[u] = ok;
+    }
+  };
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < G::LA; ++u) {
+      T2 v;
+      v.x = oka[u] ? ra[u].x : T(0);
+      v.y = oka[u] ? (OPA ? -ra[u].y : ra[u].y) : T(0);
+      As[buf][a_i[u]][a_k[u]] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < G::LB; ++u) {
+      T2 v;
+      v.x = okb[u] ? rb[u].x : T(0);
+      v.y = okb[u] ? (OPB ? -rb[u].y : rb[u].y) : T(0);
+      Bs[buf][b_k[u]][b_j[u]] = v;
+    }
+  };
+
+  Acc c1[WM][WN], c2[WM][WN], c3[G3 ? WM : 1][G3 ? WN : 1];
+#pragma unroll
+  for (int a = 0; a < WM; ++a)
+#pragma unroll
+    for (int b = 0; b < WN; ++b) {
+      c1[a][b] = Acc{0, 0, 0, 0};
+      c2[a][b] = Acc{0, 0, 0, 0};
+      if constexpr (G3) c3[a][b] = Acc{0, 0, 0, 0};
+    }
+  bool act[WM][WN];
+#pragma unroll
+  for (int a = 0; a < WM; ++a)
+#pragma unroll
+    for (int b = 0; b < WN; ++b)
+      act[a][b] = uniform(row0 + wrow0 + 16 * a < n && col0 + wcol0 + 16 * b < n);
+
+  // fragments of one k-step; the next k-step's fragments are read from LDS
+  // while the current MFMAs issue
+  auto read_frags = [&](int buf, int s, T2 (&fa)[WM], T2 (&fb)[WN]) {
+    const int kk = 4 * lg + s;
+#pragma unroll
+    for (int a = 0; a < WM; ++a) fa[a] = As[buf][wrow0 + 16 * a + li][kk];
+#pragma unroll
+    for (int b = 0; b < WN; ++b) fb[b] = Bs[buf][kk][wcol0 + 16 * b + li];
+  };
+  auto mma = [&](const T2 (&fa)[WM], const T2 (&fb)[WN]) {
+    if constexpr (G3) {
+      T sa[WM], sb[WN];
+#pragma unroll
+      for (int a = 0; a < WM; ++a) sa[a] = fa[a].x + fa[a].y;
+#pragma unroll
+      for (int b = 0; b < WN; ++b) sb[b] = fb[b].x + fb[b].y;
+#pragma unroll
+      for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b)
+          if (act[a][b]) {
+            c1[a][b] = C::mfma(fa[a].x, fb[b].x, c1[a][b]);
+            c2[a][b] = C::mfma(fa[a].y, fb[b].y, c2[a][b]);
+            c3[a][b] = C::mfma(sa[a], sb[b], c3[a][b]);
+          }
+    } else {
+#pragma unroll
+      for (int a = 0; a < WM; ++a) {
+        const T nai = -fa[a].y;
+#pragma unroll
+        for (int b = 0; b < WN; ++b)
+          if (act[a][b]) {
+            c1[a][b] = C::mfma(fa[a].x, fb[b].x, c1[a][b]);
+            c2[a][b] = C::mfma(fa[a].x, fb[b].y, c2[a][b]);
+            c1[a][b] = C::mfma(nai, fb[b].y, c1[a][b]);
+            c2[a][b] = C::mfma(fa[a].y, fb[b].x, c2[a][b]);
+          }
+      }
+    }
+  };
+
+  const int nchunks = (n + BK - 1) / BK;
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    const int buf = c & 1;
+    const int k0 = c * BK;
+    if (c + 1 < nchunks) load_chunk(k0 + BK);
+    // k-step s of the chunk contracts k = k0 + 4 g + s; it is needed when k0 + s < n
+    T2 fa0[WM], fb0[WN], fa1[WM], fb1[WN];
+    read_frags(buf, 0, fa0, fb0);
+    if (k0 + 1 < n) read_frags(buf, 1, fa1, fb1);
+    mma(fa0, fb0);
+    if (k0 + 1 < n) {
+      if (k0 + 2 < n) read_frags(buf, 2, fa0, fb0);
+      mma(fa1, fb1);
+      if (k0 + 2 < n) {
+        if (k0 + 3 < n) read_frags(buf, 3, fa1, fb1);
+        mma(fa0, fb0);
+        if (k0 + 3 < n) mma(fa1, fb1);
+      }
+    }
+    if (c + 1 < nchunks) store_chunk(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int a = 0; a < WM; ++a) {
+#pragma unroll
+    for (int b = 0; b < WN; ++b) {
+      const int gj = col0 + wcol0 + 16 * b + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = row0 + wrow0 + 16 * a + C::out_row(lane, v);
+        if (gi < n && gj < n) {
+          T2 o;
+          if constexpr (G3) {
+            o.x = c1[a][b][v] - c2[a][b][v];
+            o.y = c3[a][b][v] - c1[a][b][v] - c2[a][b][v];
+          } else {
+            o.x = c1[a][b][v];
+            o.y = c2[a][b][v];
+          }
+          Cg[static_cast<size_t>(gi) * n + gj] = o;
+        }
+      }
+    }
+  }
+}
+
+// Decode a logical GEMM task id into (job, mode, tile row, tile column).
+__device__ __forceinline__ void gemm_task(const GemmJob* jobs, int njobs, int id, int& jidx, int& p, int& tm,
+                                          int& tn) {
+  jidx = 0;
+  for (int j = 1; j < njobs; ++j)
+    if (id >= jobs[j].tile_begin) jidx = j;
+  const GemmJob& jb = jobs[jidx];
+  const int local = id - jb.tile_begin;
+  const int per_mode = jb.tiles_m * jb.tiles_n;
+  p = local / per_mode;
+  const int rem = local - p * per_mode;
+  tm = rem / jb.tiles_n;
+  tn = rem - tm * jb.tiles_n;
+}
+
+template <typename T, int WM, int WN, int WGM, int WGN, bool OPA, bool OPB, bool G3>
+__global__ __launch_bounds__(kWave * WGM * WGN) void k_cgemm2(GemmArgs args) {
+  __shared__ __attribute__((aligned(16))) char smem[Tile2<T, WM, WN, WGM, WGN>::kLdsBytes];
+  const int id = xcd_remap(blockIdx.x, gridDim.x);
+  int jidx, p, tm, tn;
+  gemm_task(args.jobs, args.njobs, id, jidx, p, tm, tn);
+  cgemm2_tile<T, WM, WN, WGM, WGN, OPA, OPB, G3>(args.jobs[jidx], p, tm, tn, smem);
+}
+
+}  // namespace gemm_detail
+
+// Launch the interleaved-complex product kernel with one tile configuration.
+template <typename T, int WM, int WN, int WGM, int WGN, int VER>
+hipError_t launch_cgemm_cfg(const GemmArgs& a, bool g3, hipStream_t s) {
+  using namespace gemm_detail;
+  const int oa = a.jobs[0].opA, ob = a.jobs[0].opB;   // shared by all jobs of a launch
+  constexpr int nt = kWave * WGM * WGN;
+  const int g = a.total_tiles;
+#define PM_K(OA, OB, G3)                                                           \
+  do {                                                                             \
+    if constexpr (VER == 2) k_cgemm2<T, WM, WN, WGM, WGN, OA, OB, G3><<<g, nt, 0, s>>>(a); \
+    else k_cgemm<T, WM, WN, WGM, WGN, OA, OB, G3><<<g, nt, 0, s>>>(a);              \
+  } while (0)
+  if (g3) {
+    if (!oa && !ob) PM_K(false, false, true);
+    else if (!oa && ob) PM_K(false, true, true);
+    else if (oa && !ob) PM_K(true, false, true);
+    else PM_K(true, true, true);
+  } else {
+    if (!oa && !ob) PM_K(false, false, false);
+    else if (!oa && ob) PM_K(false, true, false);
+    else if (oa && !ob) PM_K(true, false, false);
+    else PM_K(true, true, false);
+  }
+#undef PM_K
+  return hipGetLastError();
+}
+
+// Tile configurations (blocks of 16 x 16 per wavefront WM x WN, wavefronts per
+// work-group WGM x WGN).  Index order is part of the tuning table.
+#define PM_GEMM_CONFIGS(X)  \
+  X(0, 2, 2, 2, 2, 1)         \
+  X(1, 2, 2, 4, 2, 1)         \
+  X(2, 2, 1, 2, 4, 1)         \
+  X(3, 1, 4, 4, 1, 1)         \
+  X(4, 2, 2, 2, 2, 2)         \
+  X(5, 2, 2, 4, 2, 2)         \
+  X(6, 2, 1, 2, 4, 2)         \
+  X(7, 1, 4, 4, 1, 2)         \
+  X(8, 2, 4, 2, 1, 2)         \
+  X(9, 4, 2, 1, 2, 2)
+
+}  // namespace pm

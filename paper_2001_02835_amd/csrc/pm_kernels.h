@@ -90,9 +90,13 @@ struct GemmJob {
 constexpr int kMaxGemmJobs = 48;
 struct GemmArgs { GemmJob jobs[kMaxGemmJobs]; int njobs; int total_tiles; };
 
-// Tile edge of the products for a precision (rows and columns per tile).
-int gemm_tile(FourierType t);
-hipError_t launch_gemm(const GemmArgs& a, FourierType t, hipStream_t s);
+// Product tile configurations: rows x columns of C per work-group.  All jobs
+// of one launch share the configuration and the operand forms.
+struct GemmShape { int bm, bn; };
+int gemm_num_configs(FourierType t);
+GemmShape gemm_shape(FourierType t, int cfg);
+int gemm_config(FourierType t, int n);          // tuned choice for matrix size n
+hipError_t launch_gemm(const GemmArgs& a, FourierType t, int cfg, hipStream_t s);
 int gemm_tile_bf16();
 hipError_t launch_gemm_bf16(const GemmArgs& a, hipStream_t s);
 

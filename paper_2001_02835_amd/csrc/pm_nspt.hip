@@ -116,10 +116,12 @@ struct GemmBatch {
   int form;     // opA * 2 + opB
   GemmArgs a{};
   pm_status status = PM_OK;
+  int cfg = 0;
   void add(const void* A, const void* B, void* C, int n, int L) {
     if (status) return;
     if (a.njobs == kMaxGemmJobs) flush();
-    const int tile = gemm_tile(ft);
+    cfg = gemm_config(ft, n);      // one matrix size per NSPT call
+    const GemmShape sh = gemm_shape(ft, cfg);
     GemmJob& j = a.jobs[a.njobs++];
     j.A = A;
     j.B = B;
@@ -128,14 +130,14 @@ struct GemmBatch {
     j.L = L;
     j.opA = form >> 1;
     j.opB = form & 1;
-    j.tiles_m = (n + tile - 1) / tile;
-    j.tiles_n = j.tiles_m;
+    j.tiles_m = (n + sh.bm - 1) / sh.bm;
+    j.tiles_n = (n + sh.bn - 1) / sh.bn;
     j.tile_begin = a.total_tiles;
     a.total_tiles += j.tiles_m * j.tiles_n * L;
   }
   void flush() {
     if (status || a.njobs == 0) return;
-    status = st(timed(PM_PHASE_PRODUCT, s, [&] { return launch_gemm(a, ft, s); }));
+    status = st(timed(PM_PHASE_PRODUCT, s, [&] { return launch_gemm(a, ft, cfg, s); }));
     a.njobs = 0;
     a.total_tiles = 0;
   }

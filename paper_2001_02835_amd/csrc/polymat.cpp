@@ -207,35 +207,40 @@ pm_status enqueue_products(const std::vector<Planned>& items, int prec, hipStrea
     pm_status s = flush();
     if (s) return s;
   }
-  // 4. mode-wise products, one launch per operand form (and per 48 jobs)
-  for (int form = 0; form < 4; ++form) {
-    GemmArgs ga{};
-    const int tile = gemm_tile(ft);
-    auto flush = [&]() -> pm_status {
-      if (ga.njobs == 0) return PM_OK;
-      pm_status s = from_hip(timed(PM_PHASE_PRODUCT, st, [&] { return launch_gemm(ga, ft, st); }));
-      ga.njobs = 0;
-      ga.total_tiles = 0;
-      return s;
-    };
-    for (const Planned& it : items) {
-      if (it.pr.op_a * 2 + it.pr.op_b != form) continue;
-      if (ga.njobs == kMaxGemmJobs) { pm_status s = flush(); if (s) return s; }
-      GemmJob& j = ga.jobs[ga.njobs++];
-      j.A = it.ws + it.lay.At;
-      j.B = it.ws + it.lay.Bt;
-      j.C = it.ws + it.lay.Ct;
-      j.n = it.pr.n;
-      j.L = it.L;
-      j.opA = it.pr.op_a;
-      j.opB = it.pr.op_b;
-      j.tiles_m = (it.pr.n + tile - 1) / tile;
-      j.tiles_n = j.tiles_m;
-      j.tile_begin = ga.total_tiles;
-      ga.total_tiles += j.tiles_m * j.tiles_n * it.L;
+  // 4. mode-wise products, one launch per (operand form, tile configuration)
+  {
+    const int ncfg = gemm_num_configs(ft);
+    for (int form = 0; form < 4; ++form) {
+      for (int cfg = 0; cfg < ncfg; ++cfg) {
+        GemmArgs ga{};
+        const GemmShape sh = gemm_shape(ft, cfg);
+        auto flush = [&]() -> pm_status {
+          if (ga.njobs == 0) return PM_OK;
+          pm_status s = from_hip(timed(PM_PHASE_PRODUCT, st, [&] { return launch_gemm(ga, ft, cfg, st); }));
+          ga.njobs = 0;
+          ga.total_tiles = 0;
+          return s;
+        };
+        for (const Planned& it : items) {
+          if (it.pr.op_a * 2 + it.pr.op_b != form || gemm_config(ft, it.pr.n) != cfg) continue;
+          if (ga.njobs == kMaxGemmJobs) { pm_status s = flush(); if (s) return s; }
+          GemmJob& j = ga.jobs[ga.njobs++];
+          j.A = it.ws + it.lay.At;
+          j.B = it.ws + it.lay.Bt;
+          j.C = it.ws + it.lay.Ct;
+          j.n = it.pr.n;
+          j.L = it.L;
+          j.opA = it.pr.op_a;
+          j.opB = it.pr.op_b;
+          j.tiles_m = (it.pr.n + sh.bm - 1) / sh.bm;
+          j.tiles_n = (it.pr.n + sh.bn - 1) / sh.bn;
+          j.tile_begin = ga.total_tiles;
+          ga.total_tiles += j.tiles_m * j.tiles_n * it.L;
+        }
+        pm_status s = flush();
+        if (s) return s;
+      }
     }
-    pm_status s = flush();
-    if (s) return s;
   }
   // 5. inverse transforms, truncation and unscaling into C
   for (auto& kv : byL) {
