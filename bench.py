@@ -216,16 +216,16 @@ def main(argv=None):
     ms, phases = time_steps(torch, pm, items, "fp64", args.steps, args.warmup, ws, timing=True)
     value = count / (ms * 1e-3)
 
-    flops_useful = count * L * 8.0 * n ** 3           # per launch of the product kernel
+    flops_step = count * L * 8.0 * n ** 3             # useful flops of one step (8 N^3 per mode)
     pms, plaunch = phases["product"]
-    per_launch_s = pms * 1e-3 / max(plaunch, 1)
-    achieved = flops_useful / per_launch_s / 1e12
+    kernel = "k_cgemm<double> (FP64 MFMA mode-wise products, 3-product complex form)"
+    work = f"{count} products x {L} modes x 8*{n}^3 flop = {flops_step/1e9:.2f} GFLOP per launch"
+    achieved = flops_step * args.steps / (pms * 1e-3) / 1e12
     traffic = load_traffic("k_cgemm_f64_c2")
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK["fp64"], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK["fp64"], 4), "traffic": traffic,
-                "kernel": "k_cgemm<double> (mode-wise FP64 complex products, 4M on 16x16x4 MFMA)",
-                "algorithmic_work": f"{count} products x {L} modes x 8*{n}^3 flop = {flops_useful/1e9:.2f} GFLOP per launch",
-                "avg_launch_ms": round(pms / max(plaunch, 1), 4)}
+                "frac": round(achieved / PEAK["fp64"], 4), "traffic": traffic, "kernel": kernel,
+                "algorithmic_work": work, "avg_launch_ms": round(pms / max(plaunch, 1), 4),
+                "launches_per_step": plaunch // args.steps}
     phase_ms = {k: round(v[0] / args.steps, 4) for k, v in phases.items() if v[1]}
 
     out = {

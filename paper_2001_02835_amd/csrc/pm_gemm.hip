@@ -38,6 +38,8 @@ const int g_force_cfg = env_int("POLYMAT_GEMM_CONFIG", -1);
 
 }  // namespace
 
+bool gemm_uses_g3() { return g_gemm_g3; }
+
 int gemm_num_configs(FourierType t) { return t == kBF16Split ? 1 : kNumShapes; }
 
 GemmShape gemm_shape(FourierType t, int cfg) {

@@ -96,6 +96,7 @@ struct GemmShape { int bm, bn; };
 int gemm_num_configs(FourierType t);
 GemmShape gemm_shape(FourierType t, int cfg);
 int gemm_config(FourierType t, int n);          // tuned choice for matrix size n
+bool gemm_uses_g3();                            // three-product complex form in use
 hipError_t launch_gemm(const GemmArgs& a, FourierType t, int cfg, hipStream_t s);
 int gemm_tile_bf16();
 hipError_t launch_gemm_bf16(const GemmArgs& a, hipStream_t s);
