@@ -35,9 +35,15 @@ PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # dense MFMA TFLOP/s, M
 HBM_PEAK_GBS = 8000.0
 
 
+GEMM_SOURCES = ("pm_gemm_impl.h", "pm_gemm_f64.hip", "pm_gemm.hip", "pm_gemm_tuning.h", "pm_common.h")
+
+
 def gemm_source_hash() -> str:
-    p = os.path.join(ROOT, "paper_2001_02835_amd", "csrc", "pm_gemm.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """Hash of the sources that define the FP64 product kernel and its shape choice."""
+    h = hashlib.sha256()
+    for name in GEMM_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2001_02835_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(kernel_key: str):

@@ -1,7 +1,7 @@
 // Device building blocks of the order-axis transforms (FFT-CONV Steps 2 and
 // 4, eqs. (7) and (9)), shared by the product pipeline and the NSPT step.
 //
-// One work-group of four wavefronts handles 64 consecutive matrix entries
+// One work-group of four wavefronts handles ENT consecutive matrix entries
 // (lanes run over entries, so every global access of a wavefront is a
 // contiguous run).  With L = 4M and at most 2M nonzero orders:
 //   forward  At[4q + r] = sum_{m<M} w_M^{mq} c_r[m],  c_r[m] = w_L^{mr} (a[m] + i^r a[m+M])
@@ -9,7 +9,11 @@
 //   inverse  sum_p Ct[p] w_L^{-kp} = sum_r w_L^{-kr} d_r[k mod M],
 //            d_r = length-M inverse DFT of the modes p = 4q + r,
 // with wavefront r handling residue r and the residues combined in LDS in a
-// fixed order (bitwise reproducible).
+// fixed order (bitwise reproducible).  For L <= 64 one lane holds one entry
+// (ENT = 64).  For L = 128 two lanes share an entry (ENT = 32): the
+// length-M DFT of a residue is split into its even and odd outputs (forward)
+// or inputs (inverse), one per half-wavefront, which halves both the LDS tile
+// of a work-group and the registers of a lane.
 #pragma once
 
 #include "pm_common.h"
@@ -17,8 +21,17 @@
 
 namespace pm {
 
-constexpr int kEnt = 64;        // entries per work-group
+constexpr int kEnt = 64;        // entries per work-group for L <= 64
 constexpr int kFftThreads = 256;
+
+// lanes per matrix entry and entries per work-group for transform length L
+template <int L> constexpr int fft_split() { return L >= 128 ? 2 : 1; }
+template <int L> constexpr int fft_ent() { return kEnt / fft_split<L>(); }
+// occupancy floor (waves per SIMD) given to the compiler: the split form
+// keeps few values live, so keep the register allocation within 3 waves
+template <int L> constexpr int fft_min_waves() { return L >= 128 ? 3 : 1; }
+// the same for a run-time L (grid sizes)
+inline int fft_entries_per_group(int L) { return L >= 128 ? kEnt / 2 : kEnt; }
 
 // ------------------------------------------------------------ BF16 split
 
@@ -81,103 +94,162 @@ __device__ __forceinline__ double2 load_mode(const void* src, int E, int p, int 
 
 // ------------------------------------------------------------ forward
 
-// Residue R of the forward transform of the orders staged in tile[k][lane]
-// (k < nord, already rescaled), stored as modes 4q + R.
+// Residue R of the forward transform of the orders staged in tile[k][el]
+// (already rescaled), stored as modes 4q + R.  Every row k < L/2 of the tile
+// is read: the caller zero-fills the rows from nord on (branch-free loads let
+// the compiler interleave them with the arithmetic).
 template <int L, int R, FourierType FT>
-__device__ __forceinline__ void forward_residue(const double2 (*tile)[kEnt], int nord, int lane, void* dst,
-                                                int E, int n, int e, bool valid) {
+__device__ __forceinline__ void forward_residue(const double2 (*tile)[fft_ent<L>()], int lane,
+                                                void* dst, int E, int n, int e, bool valid) {
   constexpr int M = L / 4;
-  double2 c[M];
-  static_for<0, M>([&](auto mi) {
-    constexpr int m = decltype(mi)::value;
-    double2 a0 = (m < nord) ? tile[m][lane] : make_double2(0.0, 0.0);
-    double2 a1 = (m + M < nord) ? tile[m + M][lane] : make_double2(0.0, 0.0);
-    double2 t = cadd(a0, cmul_ipow<R>(a1));
-    c[m] = ctwiddle<m * R, L, +1>(t);
-  });
-  dft_inplace<M, +1>(c);
-  if (valid) {
-    static_for<0, M>([&](auto qi) {
-      constexpr int q = decltype(qi)::value;
-      store_mode<FT>(dst, E, n, 4 * q + R, e, c[q]);
+  constexpr int ENT = fft_ent<L>();
+  if constexpr (fft_split<L>() == 1) {
+    double2 c[M];
+    static_for<0, M>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      const double2 a0 = tile[m][lane];
+      const double2 a1 = tile[m + M][lane];
+      c[m] = ctwiddle<m * R, L, +1>(cadd(a0, cmul_ipow<R>(a1)));
     });
+    dft_inplace<M, +1>(c);
+    if (valid) {
+      static_for<0, M>([&](auto qi) {
+        constexpr int q = decltype(qi)::value;
+        store_mode<FT>(dst, E, n, 4 * q + R, e, c[q]);
+      });
+    }
+  } else {
+    // half h of the wavefront forms the outputs q = 2 q' + h:
+    //   X[2q' + h] = sum_{m < M/2} (c[m] + (-1)^h c[m + M/2]) w_M^{m h} w_{M/2}^{m q'}
+    constexpr int M2 = M / 2;
+    const int el = lane % ENT;
+    const bool odd = lane >= ENT;
+    const double sg = odd ? -1.0 : 1.0;
+    auto cval = [&](auto ci) {
+      constexpr int mm = decltype(ci)::value;
+      const double2 a0 = tile[mm][el];
+      const double2 a1 = tile[mm + M][el];
+      return ctwiddle<mm * R, L, +1>(cadd(a0, cmul_ipow<R>(a1)));
+    };
+    double2 t[M2];
+    static_for<0, M2>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      const double2 lo = cval(std::integral_constant<int, m>{});
+      const double2 hi = cval(std::integral_constant<int, m + M2>{});
+      const double2 v = make_double2(lo.x + sg * hi.x, lo.y + sg * hi.y);
+      t[m] = odd ? ctwiddle<m, M, +1>(v) : v;
+    });
+    dft_inplace<M2, +1>(t);
+    if (valid) {
+      static_for<0, M2>([&](auto qi) {
+        constexpr int q = decltype(qi)::value;
+        store_mode<FT>(dst, E, n, 4 * (2 * q + (odd ? 1 : 0)) + R, e, t[q]);
+      });
+    }
   }
 }
 
 template <int L, FourierType FT>
-__device__ __forceinline__ void forward_from_tile(const double2 (*tile)[kEnt], int nord, int lane, int r,
+__device__ __forceinline__ void forward_from_tile(const double2 (*tile)[fft_ent<L>()], int lane, int r,
                                                   void* dst, int E, int n, int e, bool valid) {
   switch (r) {
-    case 0: forward_residue<L, 0, FT>(tile, nord, lane, dst, E, n, e, valid); break;
-    case 1: forward_residue<L, 1, FT>(tile, nord, lane, dst, E, n, e, valid); break;
-    case 2: forward_residue<L, 2, FT>(tile, nord, lane, dst, E, n, e, valid); break;
-    default: forward_residue<L, 3, FT>(tile, nord, lane, dst, E, n, e, valid); break;
+    case 0: forward_residue<L, 0, FT>(tile, lane, dst, E, n, e, valid); break;
+    case 1: forward_residue<L, 1, FT>(tile, lane, dst, E, n, e, valid); break;
+    case 2: forward_residue<L, 2, FT>(tile, lane, dst, E, n, e, valid); break;
+    default: forward_residue<L, 3, FT>(tile, lane, dst, E, n, e, valid); break;
   }
 }
 
 // ------------------------------------------------------------ inverse
 
-// acc[k][lane] <- sum_p Ct[p] w^{-kp} for k < nord (no 1/L), from the modes
-// d[q] = Ct[4q + R] of this thread's entry (d is overwritten).  Ends with a
+// Number of modes a lane loads for residue R, and the mode of its q-th one.
+template <int L> constexpr int lane_nmodes() { return L / 4 / fft_split<L>(); }
+template <int L, int R>
+__device__ __forceinline__ int lane_mode(int q, int lane) {
+  if constexpr (fft_split<L>() == 1) return 4 * q + R;
+  else return 4 * (2 * q + (lane >= fft_ent<L>() ? 1 : 0)) + R;
+}
+
+// acc[k][el] <- sum_p Ct[p] w^{-kp} for all k < L/2 (no 1/L), from the modes
+// d[q] = Ct[lane_mode<L,R>(q)] of this lane (d is overwritten).  Ends with a
 // barrier, after which every wavefront may read acc.
 template <int L, int R>
-__device__ __forceinline__ void inverse_from_modes(double2* d, double2 (*acc)[kEnt], int nord, int lane) {
+__device__ __forceinline__ void inverse_from_modes(double2* d, double2 (*acc)[fft_ent<L>()], int lane) {
   constexpr int M = L / 4;
-  dft_inplace<M, -1>(d);
-  auto term = [&](auto ki) {
-    constexpr int k = decltype(ki)::value;
-    return ctwiddle<k * R, L, -1>(d[k % M]);
-  };
-  // fixed order: r = 0 writes, r = 1, 2, 3 add
-  if constexpr (R == 0) {
-    static_for<0, 2 * M>([&](auto ki) {
+  constexpr int ENT = fft_ent<L>();
+  if constexpr (fft_split<L>() == 1) {
+    dft_inplace<M, -1>(d);
+    auto term = [&](auto ki) {
       constexpr int k = decltype(ki)::value;
-      if (k < nord) acc[k][lane] = term(ki);
-    });
+      return ctwiddle<k * R, L, -1>(d[k % M]);
+    };
+    // fixed order: r = 0 writes, r = 1, 2, 3 add
+    for (int w = 0; w < 4; ++w) {
+      if (w == R) {
+        static_for<0, 2 * M>([&](auto ki) {
+          constexpr int k = decltype(ki)::value;
+          acc[k][lane] = (R == 0) ? term(ki) : cadd(acc[k][lane], term(ki));
+        });
+      }
+      __syncthreads();
+    }
+  } else {
+    // half h holds the length-M/2 inverse DFT of the even (h = 0) or odd
+    // (h = 1) modes of residue R; with the partner half's values,
+    //   Y[j] = E[j] + w_M^-j O[j],  Y[j + M/2] = E[j] - w_M^-j O[j],
+    // and half h keeps Y[j + h M/2], j < M/2.
+    constexpr int M2 = M / 2;
+    const int el = lane % ENT;
+    const bool odd = lane >= ENT;
+    dft_inplace<M2, -1>(d);
+    // orders k = j + h M/2 and k = j + h M/2 + M; term w_L^{-kR} Y[j + h M/2].
+    // The exchange sits inside the residue's turn of the chain so that only
+    // d stays live (the whole wavefront takes the same turn).
+    for (int w = 0; w < 4; ++w) {
+      if (w == R) {
+        static_for<0, M2>([&](auto ji) {
+          constexpr int j = decltype(ji)::value;
+          double2 other;
+          other.x = __shfl_xor(d[j].x, ENT);
+          other.y = __shfl_xor(d[j].y, ENT);
+          const double2 ev = odd ? other : d[j];
+          const double2 od = ctwiddle<-j, M, +1>(odd ? d[j] : other);
+          const double2 y = odd ? csub(ev, od) : cadd(ev, od);
+          static_for<0, 2>([&](auto ti) {
+            constexpr int t = decltype(ti)::value;
+            constexpr int k_even = j + t * M, k_odd = j + M2 + t * M;
+            const double2 te = ctwiddle<k_even * R, L, -1>(y);
+            const double2 to = ctwiddle<k_odd * R, L, -1>(y);
+            const int k = odd ? k_odd : k_even;
+            const double2 v = odd ? to : te;
+            acc[k][el] = (R == 0) ? v : cadd(acc[k][el], v);
+          });
+        });
+      }
+      __syncthreads();
+    }
   }
-  __syncthreads();
-  if constexpr (R == 1) {
-    static_for<0, 2 * M>([&](auto ki) {
-      constexpr int k = decltype(ki)::value;
-      if (k < nord) acc[k][lane] = cadd(acc[k][lane], term(ki));
-    });
-  }
-  __syncthreads();
-  if constexpr (R == 2) {
-    static_for<0, 2 * M>([&](auto ki) {
-      constexpr int k = decltype(ki)::value;
-      if (k < nord) acc[k][lane] = cadd(acc[k][lane], term(ki));
-    });
-  }
-  __syncthreads();
-  if constexpr (R == 3) {
-    static_for<0, 2 * M>([&](auto ki) {
-      constexpr int k = decltype(ki)::value;
-      if (k < nord) acc[k][lane] = cadd(acc[k][lane], term(ki));
-    });
-  }
-  __syncthreads();
 }
 
 // Same, where load(p) returns mode p of this thread's entry.
 template <int L, int R, typename Load>
-__device__ __forceinline__ void inverse_residue(Load&& load, double2 (*acc)[kEnt], int nord, int lane) {
-  constexpr int M = L / 4;
-  double2 d[M];
-  static_for<0, M>([&](auto qi) {
+__device__ __forceinline__ void inverse_residue(Load&& load, double2 (*acc)[fft_ent<L>()], int lane) {
+  constexpr int NQ = lane_nmodes<L>();
+  double2 d[NQ];
+  static_for<0, NQ>([&](auto qi) {
     constexpr int q = decltype(qi)::value;
-    d[q] = load(4 * q + R);
+    d[q] = load(lane_mode<L, R>(q, lane));
   });
-  inverse_from_modes<L, R>(d, acc, nord, lane);
+  inverse_from_modes<L, R>(d, acc, lane);
 }
 
 template <int L, typename Load>
-__device__ __forceinline__ void inverse_to_lds(Load&& load, double2 (*acc)[kEnt], int nord, int lane, int r) {
+__device__ __forceinline__ void inverse_to_lds(Load&& load, double2 (*acc)[fft_ent<L>()], int lane, int r) {
   switch (r) {
-    case 0: inverse_residue<L, 0>(load, acc, nord, lane); break;
-    case 1: inverse_residue<L, 1>(load, acc, nord, lane); break;
-    case 2: inverse_residue<L, 2>(load, acc, nord, lane); break;
-    default: inverse_residue<L, 3>(load, acc, nord, lane); break;
+    case 0: inverse_residue<L, 0>(load, acc, lane); break;
+    case 1: inverse_residue<L, 1>(load, acc, lane); break;
+    case 2: inverse_residue<L, 2>(load, acc, lane); break;
+    default: inverse_residue<L, 3>(load, acc, lane); break;
   }
 }
 

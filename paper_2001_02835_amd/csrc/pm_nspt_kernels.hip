@@ -26,26 +26,33 @@ namespace {
 // ----------------------------------------------------------- re-truncation
 
 template <int L, FourierType FIN, FourierType FOUT>
-__global__ __launch_bounds__(kFftThreads) void k_retrunc(RetruncArgs args) {
-  __shared__ double2 acc[L / 2][kEnt];
+__global__ __launch_bounds__(kFftThreads, fft_min_waves<L>()) void k_retrunc(RetruncArgs args) {
+  constexpr int ENT = fft_ent<L>();
+  constexpr int KSTEP = kFftThreads / ENT;
+  __shared__ double2 acc[L / 2][ENT];
   const RetruncJob& jb = args.jobs[blockIdx.y];
   const int E = jb.E;
-  const int e0 = blockIdx.x * kEnt;
+  const int e0 = blockIdx.x * ENT;
   if (e0 >= E) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int r = threadIdx.x / kWave;
-  const int e = e0 + lane;
+  const int el = threadIdx.x % ENT;
+  const int e = e0 + el;
   const bool valid = e < E;
   const int nord = jb.nord;
   if (jb.src) {
     auto load = [&](int p) { return valid ? load_mode<FIN>(jb.src, E, p, e) : make_double2(0.0, 0.0); };
-    inverse_to_lds<L>(load, acc, nord, lane, r);
+    inverse_to_lds<L>(load, acc, lane, r);
   }
   // time-domain value of order k: (1/L) inverse + addends (+ identity at order 0)
   const int n = jb.n;
   const bool diag = valid && (e / n) == (e - (e / n) * n);
-  for (int k = r; k < nord; k += 4) {
-    double2 x = jb.src ? cscale(acc[k][lane], 1.0 / L) : make_double2(0.0, 0.0);
+  for (int k = threadIdx.x / ENT; k < L / 2; k += KSTEP) {
+    if (k >= nord) {            // zero padding of the forward transform
+      acc[k][el] = make_double2(0.0, 0.0);
+      continue;
+    }
+    double2 x = jb.src ? cscale(acc[k][el], 1.0 / L) : make_double2(0.0, 0.0);
     if (valid) {
       for (int a = 0; a < args.nadd; ++a) {
         const double2 y = jb.add[static_cast<size_t>(a) * jb.add_stride + static_cast<size_t>(k) * E + e];
@@ -54,42 +61,45 @@ __global__ __launch_bounds__(kFftThreads) void k_retrunc(RetruncArgs args) {
       if (k == 0 && diag) x = cadd(x, args.idcoef);
       if (jb.tdst) jb.tdst[static_cast<size_t>(k) * E + e] = x;
     }
-    acc[k][lane] = x;
+    acc[k][el] = x;
   }
   __syncthreads();
-  forward_from_tile<L, FOUT>(acc, nord, lane, r, jb.dst, E, n, e, valid);
+  forward_from_tile<L, FOUT>(acc, lane, r, jb.dst, E, n, e, valid);
 }
 
 // --------------------------------------------- inverse of a weighted sum
 
 template <int L, FourierType FIN, int NSRC>
-__global__ __launch_bounds__(kFftThreads) void k_inv_combine(CombineArgs args) {
-  __shared__ double2 acc[L / 2][kEnt];
+__global__ __launch_bounds__(kFftThreads, fft_min_waves<L>()) void k_inv_combine(CombineArgs args) {
+  constexpr int ENT = fft_ent<L>();
+  constexpr int KSTEP = kFftThreads / ENT;
+  __shared__ double2 acc[L / 2][ENT];
   const CombineJob& jb = args.jobs[blockIdx.y];
   const int E = jb.E;
-  const int e0 = blockIdx.x * kEnt;
+  const int e0 = blockIdx.x * ENT;
   if (e0 >= E) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int r = threadIdx.x / kWave;
-  const int e = e0 + lane;
+  const int el = threadIdx.x % ENT;
+  const int e = e0 + el;
   const bool valid = e < E;
   const int ec = valid ? e : 0;        // clamped entry: loads stay in bounds, the result is not stored
-  constexpr int M = L / 4;
-  // modes 4q + r of sum_src coef * src, one source at a time (bounded registers)
+  constexpr int NQ = lane_nmodes<L>();
+  // this lane's modes of sum_src coef * src, one source at a time (bounded registers)
   auto build = [&](auto rc) {
     constexpr int R = decltype(rc)::value;
-    double2 d[M];
-    static_for<0, M>([&](auto qi) { d[decltype(qi)::value] = make_double2(0.0, 0.0); });
+    double2 d[NQ];
+    static_for<0, NQ>([&](auto qi) { d[decltype(qi)::value] = make_double2(0.0, 0.0); });
 #pragma unroll 1
     for (int q = 0; q < NSRC; ++q) {
       const void* src = jb.src[q];
       const double2 c = jb.coef[q];
-      static_for<0, M>([&](auto qi) {
+      static_for<0, NQ>([&](auto qi) {
         constexpr int m = decltype(qi)::value;
-        d[m] = cadd(d[m], cmul(c, load_mode<FIN>(src, E, 4 * m + R, ec)));
+        d[m] = cadd(d[m], cmul(c, load_mode<FIN>(src, E, lane_mode<L, R>(m, lane), ec)));
       });
     }
-    inverse_from_modes<L, R>(d, acc, jb.nord, lane);
+    inverse_from_modes<L, R>(d, acc, lane);
   };
   switch (r) {
     case 0: build(std::integral_constant<int, 0>{}); break;
@@ -98,8 +108,8 @@ __global__ __launch_bounds__(kFftThreads) void k_inv_combine(CombineArgs args) {
     default: build(std::integral_constant<int, 3>{}); break;
   }
   if (valid)
-    for (int k = r; k < jb.nord; k += 4)
-      if (k >= jb.kmin) jb.dst[static_cast<size_t>(k) * E + e] = cscale(acc[k][lane], jb.rec->sinv[k]);
+    for (int k = threadIdx.x / ENT; k < jb.nord; k += KSTEP)
+      if (k >= jb.kmin) jb.dst[static_cast<size_t>(k) * E + e] = cscale(acc[k][el], jb.rec->sinv[k]);
 }
 
 // ------------------------------------------------------------------ trace
@@ -203,7 +213,8 @@ hipError_t combine_dispatch(const CombineArgs& a, int L, dim3 g, hipStream_t s) 
 hipError_t launch_retrunc(const RetruncArgs& a, int L, int max_entries, FourierType fin, FourierType fout,
                           hipStream_t s) {
   if (a.njobs <= 0) return hipSuccess;
-  dim3 g((max_entries + kEnt - 1) / kEnt, a.njobs);
+  const int ent = fft_entries_per_group(L);
+  dim3 g((max_entries + ent - 1) / ent, a.njobs);
   if (fin == kF64) return retrunc_dispatch<kF64, kF64>(a, L, g, s);
   if (fout == kF32) return retrunc_dispatch<kF32, kF32>(a, L, g, s);
   return retrunc_dispatch<kF32, kBF16Split>(a, L, g, s);
@@ -211,7 +222,8 @@ hipError_t launch_retrunc(const RetruncArgs& a, int L, int max_entries, FourierT
 
 hipError_t launch_inv_combine(const CombineArgs& a, int L, int max_entries, FourierType fin, hipStream_t s) {
   if (a.njobs <= 0) return hipSuccess;
-  dim3 g((max_entries + kEnt - 1) / kEnt, a.njobs);
+  const int ent = fft_entries_per_group(L);
+  dim3 g((max_entries + ent - 1) / ent, a.njobs);
   // every job of one launch has the same number of sources (1 or kMaxCombine)
   const int ns = a.jobs[0].nsrc;
   for (int j = 1; j < a.njobs; ++j)

@@ -11,8 +11,8 @@
 //   At[4q + r] = sum_{m<M} w_M^{mq} c_r[m],   c_r[m] = w_L^{mr} (a[m] + i^r a[m+M])
 // i.e. one pruned radix-4 step (the upper half of the padded input is zero)
 // followed by a length-M DFT per residue r.  A work-group of four wavefronts
-// covers 64 entries; wavefront r computes residue r from the input tile
-// staged in LDS.
+// covers 64 entries (32 at L = 128, where two lanes share an entry);
+// wavefront r computes residue r from the input tile staged in LDS.
 //
 // Inverse: wavefront r loads the modes p = 4q + r, runs a length-M inverse
 // DFT d_r, and the four residues are combined as
@@ -25,41 +25,47 @@ namespace pm {
 namespace {
 
 template <int L, FourierType FT>
-__global__ __launch_bounds__(kFftThreads) void k_forward(FwdArgs args) {
-  __shared__ double2 tile[L / 2][kEnt];
+__global__ __launch_bounds__(kFftThreads, fft_min_waves<L>()) void k_forward(FwdArgs args) {
+  constexpr int ENT = fft_ent<L>();
+  constexpr int KSTEP = kFftThreads / ENT;   // orders staged per pass
+  __shared__ double2 tile[L / 2][ENT];
   const FwdJob& jb = args.jobs[blockIdx.y];
-  const int e0 = blockIdx.x * kEnt;
+  const int e0 = blockIdx.x * ENT;
   if (e0 >= jb.E) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int r = threadIdx.x / kWave;
-  const int e = e0 + lane;
+  const int el = threadIdx.x % ENT;
+  const int e = e0 + el;
   const bool valid = e < jb.E;
-  // Step 1 fused: rescale by s^k while staging orders k = r, r+4, ...; the
-  // zero padding is never stored (orders >= nord read as zero).
-  for (int k = r; k < jb.nord; k += 4) {
-    double2 v = valid ? jb.src[static_cast<size_t>(k) * jb.E + e] : make_double2(0.0, 0.0);
-    tile[k][lane] = cscale(v, jb.rec->spow[k]);
+  // Step 1 fused: rescale by s^k while staging; the zero padding of Step 2
+  // only exists in LDS (rows nord .. L/2-1).
+  for (int k = threadIdx.x / ENT; k < L / 2; k += KSTEP) {
+    double2 v = (valid && k < jb.nord) ? jb.src[static_cast<size_t>(k) * jb.E + e] : make_double2(0.0, 0.0);
+    tile[k][el] = k < jb.nord ? cscale(v, jb.rec->spow[k]) : v;
   }
   __syncthreads();
-  forward_from_tile<L, FT>(tile, jb.nord, lane, r, jb.dst, jb.E, jb.n, e, valid);
+  forward_from_tile<L, FT>(tile, lane, r, jb.dst, jb.E, jb.n, e, valid);
 }
 
 template <int L, FourierType FT>
-__global__ __launch_bounds__(kFftThreads) void k_inverse(InvArgs args) {
-  __shared__ double2 acc[L / 2][kEnt];
+__global__ __launch_bounds__(kFftThreads, fft_min_waves<L>()) void k_inverse(InvArgs args) {
+  constexpr int ENT = fft_ent<L>();
+  constexpr int KSTEP = kFftThreads / ENT;
+  __shared__ double2 acc[L / 2][ENT];
   const InvJob& jb = args.jobs[blockIdx.y];
-  const int e0 = blockIdx.x * kEnt;
+  const int e0 = blockIdx.x * ENT;
   if (e0 >= jb.E) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int r = threadIdx.x / kWave;
-  const int e = e0 + lane;
+  const int el = threadIdx.x % ENT;
+  const int e = e0 + el;
   const bool valid = e < jb.E;
   auto load = [&](int p) { return valid ? load_mode<FT>(jb.src, jb.E, p, e) : make_double2(0.0, 0.0); };
-  inverse_to_lds<L>(load, acc, jb.nord, lane, r);
+  inverse_to_lds<L>(load, acc, lane, r);
   // Steps 4-5: 1/L, unscale by s^-k (one table), keep orders < nord
   if (valid)
-    for (int k = r; k < jb.nord; k += 4)
-      jb.dst[static_cast<size_t>(k) * jb.E + e] = cscale(acc[k][lane], jb.rec->sinv[k]);
+    for (int k = threadIdx.x / ENT; k < jb.nord; k += KSTEP)
+      jb.dst[static_cast<size_t>(k) * jb.E + e] = cscale(acc[k][el], jb.rec->sinv[k]);
 }
 
 // ------------------------------------------------------------ norms / scale
@@ -211,7 +217,8 @@ hipError_t inv_dispatch(const InvArgs& a, int L, dim3 grid, hipStream_t s) {
 
 hipError_t launch_forward(const FwdArgs& a, int L, int max_entries, FourierType t, hipStream_t s) {
   if (a.njobs <= 0) return hipSuccess;
-  dim3 grid((max_entries + kEnt - 1) / kEnt, a.njobs);
+  const int ent = fft_entries_per_group(L);
+  dim3 grid((max_entries + ent - 1) / ent, a.njobs);
   switch (t) {
     case kF64: return fwd_dispatch<kF64>(a, L, grid, s);
     case kF32: return fwd_dispatch<kF32>(a, L, grid, s);
@@ -221,7 +228,8 @@ hipError_t launch_forward(const FwdArgs& a, int L, int max_entries, FourierType 
 
 hipError_t launch_inverse(const InvArgs& a, int L, int max_entries, FourierType t, hipStream_t s) {
   if (a.njobs <= 0) return hipSuccess;
-  dim3 grid((max_entries + kEnt - 1) / kEnt, a.njobs);
+  const int ent = fft_entries_per_group(L);
+  dim3 grid((max_entries + ent - 1) / ent, a.njobs);
   switch (t) {
     case kF64: return inv_dispatch<kF64>(a, L, grid, s);
     default: return inv_dispatch<kF32>(a, L, grid, s);
