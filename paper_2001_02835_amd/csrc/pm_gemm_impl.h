@@ -276,21 +276,19 @@ __global__ __launch_bounds__(kWave * WGM * WGN) void k_cgemm(GemmArgs args) {
 }
 
 
-// Second form of the kernel: both operand tiles keep their natural row-major
-// layout in LDS (A as [i][k], B as [k][j], rows padded by one element so that
-// staging stores and fragment reads are free of bank conflicts), and the k
-// index is permuted across the lane groups of the MFMA: in k-step s of a
-// chunk, lane group g (lanes 16g..16g+15) contracts over k = 4g + s.  The
-// MFMA only needs A and B to agree on that assignment.  In full chunks the
-// fragments of two k-steps are read at once (the next two while the current
-// ones are multiplied) and each accumulator receives its two updates back to
-// back, which keeps the FP64 MFMA pipe busier than alternating accumulators.
+// Second form of the kernel: both operand tiles are staged k-major in LDS
+// (A as [k][i], B as [k][j], rows padded by one element), so that every
+// fragment read is a contiguous run across the 16 lanes of a lane group, and
+// the k index is permuted across the lane groups of the MFMA: in k-step s of
+// a chunk, lane group g (lanes 16g..16g+15) contracts over k = 4g + s.  The
+// MFMA only needs A and B to agree on that assignment.  The fragments of the
+// next k-step are read from LDS while the current MFMAs issue.
 template <typename T, int WM, int WN, int WGM, int WGN>
 struct Tile2 {
   using T2 = typename Cx<T>::T2;
   using G = GemmCfg<T, WM, WN, WGM, WGN>;
   static constexpr int BM = G::BM, BN = G::BN, BK = G::BK;
-  static constexpr int kAElems = 2 * BM * (BK + 1);
+  static constexpr int kAElems = 2 * BK * (BM + 1);
   static constexpr int kBElems = 2 * BK * (BN + 1);
   static constexpr size_t kLdsBytes = sizeof(T2) * (kAElems + kBElems);
 };
@@ -302,10 +300,10 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
   using Acc = typename C::Acc;
   using G = GemmCfg<T, WM, WN, WGM, WGN>;
   constexpr int BM = G::BM, BN = G::BN, BK = G::BK, NT = G::NT;
-  typedef T2 ATile[BM][BK + 1];
+  typedef T2 ATile[BK][BM + 1];
   typedef T2 BTile[BK][BN + 1];
   ATile* As = reinterpret_cast<ATile*>(smem);
-  BTile* Bs = reinterpret_cast<BTile*>(smem + sizeof(T2) * 2 * BM * (BK + 1));
+  BTile* Bs = reinterpret_cast<BTile*>(smem + sizeof(T2) * Tile2<T, WM, WN, WGM, WGN>::kAElems);
 
   const int n = jb.n, L = jb.L;
   const size_t E = static_cast<size_t>(n) * n;
@@ -362,7 +360,7 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
       T2 v;
       v.x = oka[u] ? ra[u].x : T(0);
       v.y = oka[u] ? (OPA ? -ra[u].y : ra[u].y) : T(0);
-      As[buf][a_i[u]][a_k[u]] = v;
+      As[buf][a_k[u]][a_i[u]] = v;
     }
 #pragma unroll
     for (int u = 0; u < G::LB; ++u) {
@@ -382,21 +380,56 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
       c2[a][b] = Acc{0, 0, 0, 0};
       if constexpr (G3) c3[a][b] = Acc{0, 0, 0, 0};
     }
-  bool act[WM][WN];
+  // Thin edge: when n = 16 m + 1 the last block row and block column hold a
+  // single row / column of C.  Instead of a whole 16x16 MFMA block, such a
+  // block is accumulated on the vector unit (about 1/16 of the work): its
+  // fragment of the thin side is the broadcast of the one row (column) of the
+  // operand, every lane sums its own k subset (k = 4 g + s) of the complex
+  // product into components 0 (re) and 1 (im) of the block's unused MFMA
+  // accumulator, and the four lane groups are summed at the end.  This removes
+  // 2/(m+1) of the MFMA work.
+  const bool thin = uniform((n & 15) == 1 && n > 16);
+  const int edge = n - 1;                              // the thin row / column
+  bool rin[WM], cin[WN], trow[WM], tcol[WN];
+#pragma unroll
+  for (int a = 0; a < WM; ++a) {
+    rin[a] = uniform(row0 + wrow0 + 16 * a < n);
+    trow[a] = uniform(thin && row0 + wrow0 + 16 * a == edge);
+  }
+#pragma unroll
+  for (int b = 0; b < WN; ++b) {
+    cin[b] = uniform(col0 + wcol0 + 16 * b < n);
+    tcol[b] = uniform(thin && col0 + wcol0 + 16 * b == edge);
+  }
+  bool act[WM][WN], thn[WM][WN];
 #pragma unroll
   for (int a = 0; a < WM; ++a)
 #pragma unroll
-    for (int b = 0; b < WN; ++b)
-      act[a][b] = uniform(row0 + wrow0 + 16 * a < n && col0 + wcol0 + 16 * b < n);
+    for (int b = 0; b < WN; ++b) {
+      act[a][b] = rin[a] && cin[b] && !trow[a] && !tcol[b];
+      thn[a][b] = rin[a] && cin[b] && (trow[a] || tcol[b]);
+    }
+  bool wave_thin = false;   // this wave owns a thin block
+#pragma unroll
+  for (int a = 0; a < WM; ++a)
+#pragma unroll
+    for (int b = 0; b < WN; ++b) wave_thin = wave_thin || thn[a][b];
+  // fragment row / column of each lane: a thin block reads the single row
+  // (column) in every lane
+  int frow[WM], fcol[WN];
+#pragma unroll
+  for (int a = 0; a < WM; ++a) frow[a] = wrow0 + 16 * a + (trow[a] ? 0 : li);
+#pragma unroll
+  for (int b = 0; b < WN; ++b) fcol[b] = wcol0 + 16 * b + (tcol[b] ? 0 : li);
 
   // fragments of one k-step; the next k-step's fragments are read from LDS
   // while the current MFMAs issue
   auto read_frags = [&](int buf, int s, T2 (&fa)[WM], T2 (&fb)[WN]) {
     const int kk = 4 * lg + s;
 #pragma unroll
-    for (int a = 0; a < WM; ++a) fa[a] = As[buf][wrow0 + 16 * a + li][kk];
+    for (int a = 0; a < WM; ++a) fa[a] = As[buf][kk][frow[a]];
 #pragma unroll
-    for (int b = 0; b < WN; ++b) fb[b] = Bs[buf][kk][wcol0 + 16 * b + li];
+    for (int b = 0; b < WN; ++b) fb[b] = Bs[buf][kk][fcol[b]];
   };
   auto mma = [&](const T2 (&fa)[WM], const T2 (&fb)[WN]) {
     if constexpr (G3) {
@@ -427,6 +460,18 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
             c2[a][b] = C::mfma(fa[a].y, fb[b].x, c2[a][b]);
           }
       }
+    }
+    if (wave_thin) {
+      // not speculated: other waves keep their MFMA stream free of this code
+      asm volatile("");
+#pragma unroll
+      for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b)
+          if (thn[a][b]) {   // components 0 / 1 of the block's unused accumulator
+            c1[a][b][0] = fma(fa[a].x, fb[b].x, fma(-fa[a].y, fb[b].y, c1[a][b][0]));
+            c1[a][b][1] = fma(fa[a].x, fb[b].y, fma(fa[a].y, fb[b].x, c1[a][b][1]));
+          }
     }
   };
 
@@ -460,6 +505,7 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
   for (int a = 0; a < WM; ++a) {
 #pragma unroll
     for (int b = 0; b < WN; ++b) {
+      if (!act[a][b]) continue;
       const int gj = col0 + wcol0 + 16 * b + li;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -476,6 +522,27 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
           Cg[static_cast<size_t>(gi) * n + gj] = o;
         }
       }
+    }
+  }
+  // thin blocks: sum the four lane groups' k subsets (fixed order); lane
+  // group 0 stores the thin row / column, lane 0 the corner
+#pragma unroll
+  for (int a = 0; a < WM; ++a) {
+#pragma unroll
+    for (int b = 0; b < WN; ++b) {
+      if (!thn[a][b]) continue;
+      T re = c1[a][b][0], im = c1[a][b][1];
+      re += __shfl_xor(re, 16);
+      im += __shfl_xor(im, 16);
+      re += __shfl_xor(re, 32);
+      im += __shfl_xor(im, 32);
+      T2 o;
+      o.x = re;
+      o.y = im;
+      const int gi = trow[a] ? edge : row0 + wrow0 + 16 * a + li;
+      const int gj = tcol[b] ? edge : col0 + wcol0 + 16 * b + li;
+      const bool mine = (trow[a] && tcol[b]) ? lane == 0 : lg == 0;
+      if (mine && gi < n && gj < n) Cg[static_cast<size_t>(gi) * n + gj] = o;
     }
   }
 }

@@ -71,8 +71,10 @@ __global__ __launch_bounds__(kFftThreads, fft_min_waves<L>()) void k_inverse(Inv
 // ------------------------------------------------------------ norms / scale
 
 // partial[k][chunk] = sum of |x|^2 over the chunk of entries of order k.
+// Four independent loads per thread and pass keep enough reads in flight;
+// the sum is reduced within each wavefront, then over the four wavefronts.
 __global__ __launch_bounds__(256) void k_norms(NormArgs args) {
-  __shared__ double red[256];
+  __shared__ double red[4];
   const NormJob& jb = args.jobs[blockIdx.z];
   const int k = blockIdx.y;
   if (k >= jb.nord) return;
@@ -81,18 +83,24 @@ __global__ __launch_bounds__(256) void k_norms(NormArgs args) {
   const int b = chunk * per;
   const int e_end = min(jb.E, b + per);
   const double2* x = jb.src + static_cast<size_t>(k) * jb.E;
-  double s = 0.0;
-  for (int e = b + threadIdx.x; e < e_end; e += 256) {
-    double2 v = x[e];
-    s = fma(v.x, v.x, fma(v.y, v.y, s));
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int e = b + threadIdx.x;
+  for (; e + 768 < e_end; e += 1024) {
+    const double2 v0 = x[e], v1 = x[e + 256], v2 = x[e + 512], v3 = x[e + 768];
+    s0 = fma(v0.x, v0.x, fma(v0.y, v0.y, s0));
+    s1 = fma(v1.x, v1.x, fma(v1.y, v1.y, s1));
+    s2 = fma(v2.x, v2.x, fma(v2.y, v2.y, s2));
+    s3 = fma(v3.x, v3.x, fma(v3.y, v3.y, s3));
   }
-  red[threadIdx.x] = s;
+  for (; e < e_end; e += 256) {
+    const double2 v = x[e];
+    s0 = fma(v.x, v.x, fma(v.y, v.y, s0));
+  }
+  double sum = (s0 + s1) + (s2 + s3);
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = sum;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) jb.partial[k * kNormChunks + chunk] = red[0];
+  if (threadIdx.x == 0) jb.partial[k * kNormChunks + chunk] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // Choice of s (log s = t): with a_j = ||A^(j)||, b_j = ||B^(j)|| and
@@ -121,14 +129,18 @@ __global__ __launch_bounds__(64) void k_scale(ScaleArgs args) {
     // per-order norms: lane k holds a_k, b_k (k < nord <= 64)
     double na = 0.0, nb = 0.0;
     if (tid < nord) {
-      double sa = 0.0, sb = 0.0;
-      for (int q = 0; q < jb.nser; ++q)
+      double sa[4] = {0.0, 0.0, 0.0, 0.0}, sb[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int q = 0; q < jb.nser; ++q) {
+        const double* pa = jb.partA + (q * nord + tid) * kNormChunks;
+        const double* pb = jb.partB + (q * nord + tid) * kNormChunks;
+#pragma unroll
         for (int c = 0; c < kNormChunks; ++c) {
-          sa += jb.partA[(q * nord + tid) * kNormChunks + c];
-          sb += jb.partB[(q * nord + tid) * kNormChunks + c];
+          sa[c & 3] += pa[c];
+          sb[c & 3] += pb[c];
         }
-      na = sqrt(sa);
-      nb = sqrt(sb);
+      }
+      na = sqrt((sa[0] + sa[1]) + (sa[2] + sa[3]));
+      nb = sqrt((sb[0] + sb[1]) + (sb[2] + sb[3]));
     }
     // c_m = sum_j a_j b_{m-j}: lane m holds c_m (m < 64) and c_{m+64}
     double c0 = 0.0, c1 = 0.0;
@@ -149,20 +161,29 @@ __global__ __launch_bounds__(64) void k_scale(ScaleArgs args) {
     const double lmin0 = (ok0 && tid < nord) ? lc0 : kAbsent;
     const bool any = __any(ok0 && tid < nord);
     if (any) {
+      // log c_m (or the absent marker) of every m, for broadcast reads
+      __shared__ double lmax_s[128], lmin_s[64];
+      lmax_s[tid] = lmax0;
+      lmax_s[tid + 64] = lmax1;
+      lmin_s[tid] = lmin0;
+      __syncthreads();
       double lo = -300.0 / (2.0 * (nord - 1)), hi = -lo;
       for (int round = 0; round < 3; ++round) {
         const double step = (hi - lo) / 63.0;
         const double tt = lo + step * tid;
-        double mx = -kAbsent, mn = kAbsent;
-        for (int m = 0; m < 64; ++m) {
-          const double x = lane_value(lmax0, m), y = lane_value(lmin0, m);
-          mx = fmax(mx, fma(static_cast<double>(m), tt, x));
-          mn = fmin(mn, fma(static_cast<double>(m), tt, y));
+        // four independent max / min chains over m
+        double mx[4] = {-kAbsent, -kAbsent, -kAbsent, -kAbsent}, mn[4] = {kAbsent, kAbsent, kAbsent, kAbsent};
+        for (int m = 0; m < 64; m += 4) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            mx[u] = fmax(mx[u], fma(static_cast<double>(m + u), tt, lmax_s[m + u]));
+            mn[u] = fmin(mn[u], fma(static_cast<double>(m + u), tt, lmin_s[m + u]));
+          }
         }
-        for (int m = 64; m < nm; ++m) mx = fmax(mx, fma(static_cast<double>(m), tt, lane_value(lmax1, m - 64)));
+        for (int m = 64; m < nm; ++m) mx[m & 3] = fmax(mx[m & 3], fma(static_cast<double>(m), tt, lmax_s[m]));
         // arg-min over lanes; near-ties (a flat objective, e.g. only one
         // nonzero order) go to the candidate closest to t = 0 (s = 1)
-        double f = mx - mn;
+        double f = fmax(fmax(mx[0], mx[1]), fmax(mx[2], mx[3])) - fmin(fmin(mn[0], mn[1]), fmin(mn[2], mn[3]));
         int idx = tid;
         for (int off = 32; off > 0; off >>= 1) {
           const double f2 = __shfl_xor(f, off);

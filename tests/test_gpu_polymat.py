@@ -109,6 +109,25 @@ def test_batched_uneven_with_conjugated_operands():
         assert e.max() < TOL["fp64"], e
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [17, 33, 81, 161, 193, 225, 289])
+def test_thin_edge_sizes_all_operand_forms(prec, n):
+    """n = 16 m + 1: the last row and column of each mode product take the
+    vector-unit path; all four operand forms (X, X^+ on either side)."""
+    nt = 3
+    items, refs = [], []
+    for i in range(4):
+        a, b = rs(80 + i, n, nt, 0.9), rs(90 + i, n, nt, 0.9)
+        op_a, op_b = i % 2, i // 2
+        refs.append(ser.star(ser.dagger(a) if op_a else a, ser.dagger(b) if op_b else b))
+        items.append(dict(A=to_dev(a), B=to_dev(b), C=torch.empty((nt + 1, n, n), dtype=torch.complex128, device=DEV),
+                          op_a=op_a, op_b=op_b, scale=0.0))
+    pm.polymat_mul_batched(items, precision=prec)
+    for i, (it, ref) in enumerate(zip(items, refs)):
+        e = order_errors(to_host(it["C"]), ref)
+        assert e.max() < TOL[prec], (i, e)
+
+
 def test_batched_matches_single_calls_bitwise():
     a = [to_dev(rs(60 + i, 40, 15)) for i in range(3)]
     b = [to_dev(rs(70 + i, 40, 15)) for i in range(3)]
