@@ -74,3 +74,92 @@ def langevin_step(u: np.ndarray, eta: np.ndarray, z: np.ndarray, eps: float) -> 
 def langevin_step_replicas(u: np.ndarray, eta: np.ndarray, z: np.ndarray, eps: float) -> np.ndarray:
     """Replica batch: u [R, 4, ntrunc+1, N, N], eta [R, 4, N, N]."""
     return np.stack([langevin_step(u[r], eta[r], z, eps) for r in range(u.shape[0])])
+
+
+# --------------------------------------------------------------------------
+# Molecular-dynamics form of the tower (Section 2, eq. (3) and the sentence
+# after it: the truncated tower is integrated with a symplectic integrator
+# and the momenta are refreshed periodically).
+#
+# With P = (1/g) sum_{k>=1} g^k P^(k) and the fictitious time rescaled by g,
+# the equations read dU/dt = i (P * U), dP^(k)/dt = F^(k) for k >= 1, where P
+# is the series sum_{k>=1} g^k P^(k) (no order-0 term) and F^(k) is the
+# series force above.  Readings used here:
+# * the symplectic integrator is the leapfrog in kick-drift-kick order with
+#   step dt (the paper does not name one);
+# * a refresh sets P^(1) to Hermitian traceless Gaussian noise and every
+#   other order to zero (the momentum is O(1) in the full theory, i.e. it sits
+#   at order 1 of the series);
+# * the force enters at orders k >= 1 only (F^(0) vanishes at the vacuum).
+# The series Hamiltonian H = 1/2 sum_mu Tr (P_mu * P_mu) + S(U), S the action
+# of eq. (1) at beta = 1 expanded in g, is conserved order by order by the
+# exact flow; the leapfrog keeps it up to O(dt^2) per trajectory.
+# --------------------------------------------------------------------------
+
+
+def refresh_momentum(eta: np.ndarray, ntrunc: int) -> np.ndarray:
+    """Momentum series after a refresh: P^(1) = eta_mu, other orders zero.
+    eta: complex128 [4, N, N] Hermitian traceless; returns [4, ntrunc+1, N, N]."""
+    eta = np.asarray(eta, dtype=np.complex128)
+    p = np.zeros((4, ntrunc + 1) + eta.shape[1:], dtype=np.complex128)
+    if ntrunc >= 1:
+        p[:, 1] = eta
+    return p
+
+
+def md_forces(u: np.ndarray, z: np.ndarray) -> np.ndarray:
+    """F_mu^(k) for all mu, with the order-0 term set to zero."""
+    f = np.stack([series_force(u, z, mu) for mu in range(4)])
+    f[:, 0] = 0.0
+    return f
+
+
+def md_drift(u: np.ndarray, p: np.ndarray, dt: float) -> np.ndarray:
+    """U_mu <- exp(i dt P_mu) * U_mu for every mu (exact in the truncated series)."""
+    return np.stack([ser.star(ser.series_exp(1j * dt * p[mu]), u[mu]) for mu in range(4)])
+
+
+def md_trajectory(u: np.ndarray, p: np.ndarray, z: np.ndarray, dt: float, nsteps: int):
+    """Leapfrog trajectory of nsteps steps of size dt from (U, P):
+    half kick, then (drift, kick) nsteps - 1 times, drift, half kick.
+    Returns the new (U, P); the inputs are not modified."""
+    if nsteps < 1:
+        raise ValueError("nsteps must be >= 1")
+    u = np.array(u, dtype=np.complex128)
+    p = np.array(p, dtype=np.complex128)
+    p = p + 0.5 * dt * md_forces(u, z)
+    for i in range(nsteps):
+        u = md_drift(u, p, dt)
+        p = p + (dt if i < nsteps - 1 else 0.5 * dt) * md_forces(u, z)
+    return u, p
+
+
+def md_trajectory_replicas(u: np.ndarray, p: np.ndarray, z: np.ndarray, dt: float, nsteps: int):
+    """Replica batch: u, p [R, 4, ntrunc+1, N, N]."""
+    out = [md_trajectory(u[r], p[r], z, dt, nsteps) for r in range(u.shape[0])]
+    return np.stack([o[0] for o in out]), np.stack([o[1] for o in out])
+
+
+def series_action(u: np.ndarray, z: np.ndarray) -> np.ndarray:
+    """S^(k) = sum_{mu != nu} Tr[ delta_{k0} 1 - z_{mu nu} (U_mu * U_nu * U_mu^+ * U_nu^+)^(k) ],
+    eq. (1) at beta = 1 expanded in g; real for every k (the (nu, mu) term is
+    the conjugate of the (mu, nu) term).  Returns float64 [ntrunc+1]."""
+    n = u.shape[-1]
+    ud = [ser.dagger(u[m]) for m in range(4)]
+    s = np.zeros(u.shape[1], dtype=np.complex128)
+    for mu in range(4):
+        for nu in range(4):
+            if mu == nu:
+                continue
+            plaq = ser.star(ser.star(ser.star(u[mu], u[nu]), ud[mu]), ud[nu])
+            s -= z[mu, nu] * np.trace(plaq, axis1=-2, axis2=-1)
+    s[0] += 12 * n
+    return s.real
+
+
+def series_hamiltonian(u: np.ndarray, p: np.ndarray, z: np.ndarray) -> np.ndarray:
+    """H^(k) = 1/2 sum_mu Tr (P_mu * P_mu)^(k) + S^(k)  (float64 [ntrunc+1])."""
+    kin = np.zeros(u.shape[1])
+    for mu in range(4):
+        kin += 0.5 * np.trace(ser.star(p[mu], p[mu]), axis1=-2, axis2=-1).real
+    return kin + series_action(u, z)
