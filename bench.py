@@ -150,6 +150,43 @@ def bench_nspt(torch, synth, pm, dev, steps):
     return res
 
 
+def bench_md(torch, synth, pm, dev, nsteps):
+    """NSPT molecular-dynamics trajectory (leapfrog, momentum refresh): 8 replicas
+    x 4 links, SU(225) (L=15, k=4), ntrunc=31, dt=0.05, started at the twisted
+    vacuum and evolved by one warm-up trajectory."""
+    L, k, nt, dt, R = 15, 4, 31, 0.05, 8
+    n = L * L
+    u = torch.from_numpy(synth.vacuum_links(L, k, nt, replicas=R)).to(dev)
+    P = torch.zeros_like(u)
+    rng = synth.rng_for(6, 0)
+    noise = [torch.from_numpy(synth.langevin_noise(rng, R, n)).to(dev) for _ in range(2)]
+    prm = pm.nspt_params(L, k, nt, dt)
+    res = {"workload": f"8 replicas x 4 links, N=225 (L=15, k=4), ntrunc=31, leapfrog dt=0.05, "
+                       f"{nsteps} MD steps per trajectory with momentum refresh, FP64 links"}
+    for prec in ("fp64", "bf16x3"):
+        ws = pm.workspace(pm.nspt_workspace_size(R, prm, prec), dev)
+        pm.nspt_md_trajectory(u, P, prm, nsteps, eta=noise[0], precision=prec, ws=ws)
+        torch.cuda.synchronize()
+        pm.timing_read()
+        pm.timing_enable(True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        pm.nspt_md_trajectory(u, P, prm, nsteps, eta=noise[1], precision=prec, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        pm.timing_enable(False)
+        ph = pm.timing_read()
+        ms = e0.elapsed_time(e1)
+        res[prec] = {"ms_per_trajectory": round(ms, 2), "ms_per_md_step": round(ms / nsteps, 3),
+                     "force_evaluations": nsteps + 1,
+                     "phase_ms_per_trajectory": {kk: round(v[0], 3) for kk, v in ph.items() if v[1]},
+                     "paper_run_estimate_s": {"trajectories": 10, "md_steps": 40,
+                                              "seconds": round(10 * 40 * ms / nsteps / 1e3, 2)}}
+        del ws
+    return res
+
+
 def cpu_baseline(seconds: float):
     """The FP64 oracle (naive star product, BLAS matmul per term) on the host
     cores, on products of the headline shape until `seconds` have elapsed."""
@@ -187,6 +224,7 @@ def main(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-extra", action="store_true", help="skip the ntrunc = 63 precision lines")
     ap.add_argument("--nspt-steps", type=int, default=3)
+    ap.add_argument("--md-steps", type=int, default=4, help="leapfrog steps of the timed MD trajectory")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args(argv)
@@ -270,6 +308,7 @@ def main(argv=None):
     if not args.no_extra:
         out["batched_uneven"] = bench_uneven(torch, synth, pm, dev, max(args.steps // 20, 3))
         out["nspt_step"] = bench_nspt(torch, synth, pm, dev, args.nspt_steps)
+        out["nspt_md"] = bench_md(torch, synth, pm, dev, args.md_steps)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

@@ -208,10 +208,10 @@ typedef struct {
   int L;        /* twist lattice size (odd) */
   int k;        /* twist flux */
   int ntrunc;   /* truncation order */
-  double eps;   /* rescaled Langevin time step (> 0) */
+  double eps;   /* rescaled Langevin time step, or the MD step dt (> 0) */
 } nspt_params;
 
-/* Workspace bytes for nspt_langevin_step, or 0 if invalid. */
+/* Workspace bytes for nspt_langevin_step and nspt_md_trajectory, or 0 if invalid. */
 size_t nspt_workspace_size(int replicas, const nspt_params* params, int precision);
 
 /*
@@ -224,6 +224,38 @@ size_t nspt_workspace_size(int replicas, const nspt_params* params, int precisio
  */
 pm_status nspt_langevin_step(void* U, const void* eta, int replicas,
                              const nspt_params* params, int precision,
+                             void* workspace, size_t workspace_bytes,
+                             void* stream);
+
+/*
+ * One molecular-dynamics trajectory of the NSPT tower (Section 2, eq. (3)
+ * and the sentence after it: the truncated tower dU/dt = i (P * U),
+ * dP^(k)/dt = F^(k) is integrated by a symplectic integrator, with periodic
+ * momentum refreshment), for `replicas` chains at once.
+ *
+ * The momentum is the series P = sum_{k>=1} g^k P^(k) (no order-0 term),
+ * Hermitian traceless at every order; F^(k) is the force of
+ * nspt_langevin_step for k >= 1.  The integrator is the leapfrog with step
+ * dt = params->eps in kick-drift-kick order:
+ *   P <- P + dt/2 F(U);  repeat nsteps times { U_mu <- exp(i dt P_mu) * U_mu;
+ *   P <- P + dt F(U) (dt/2 after the last drift) }.
+ * All four directions move together (every force from the current links).
+ *
+ *   U    device complex128 [replicas][4][ntrunc+1][n][n], updated in place
+ *        (order 0 is left unchanged).
+ *   P    device complex128 [replicas][4][ntrunc+1][n][n], updated in place.
+ *   eta  device complex128 [replicas][4][n][n] or NULL.  When not NULL the
+ *        momentum is refreshed before the trajectory: P^(1) = eta (Hermitian
+ *        traceless), every other order zero.  When NULL the trajectory
+ *        continues from the P passed in.
+ *   nsteps  number of leapfrog steps, 1 .. 100000.
+ * The workspace is the one of nspt_langevin_step (nspt_workspace_size with
+ * the same arguments).  U, P, eta and the workspace must not overlap
+ * (PM_ERR_INVALID).  One leapfrog step after a refresh equals one
+ * nspt_langevin_step with eps = dt^2 / 2 and the same eta.
+ */
+pm_status nspt_md_trajectory(void* U, void* P, const void* eta, int replicas,
+                             const nspt_params* params, int nsteps, int precision,
                              void* workspace, size_t workspace_bytes,
                              void* stream);
 

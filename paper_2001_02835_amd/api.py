@@ -166,6 +166,29 @@ def nspt_langevin_step(U: torch.Tensor, eta: torch.Tensor, params: nat.NsptParam
     return U
 
 
+def nspt_md_trajectory(U: torch.Tensor, P: torch.Tensor, params: nat.NsptParams, nsteps: int,
+                       eta: Optional[torch.Tensor] = None, precision="fp64",
+                       ws: Optional[torch.Tensor] = None):
+    """One leapfrog trajectory (step params.eps) of U and the momentum series P,
+    both [R, 4, ntrunc+1, n, n], in place; eta [R, 4, n, n] refreshes P first."""
+    _series_check(U, "U")
+    _series_check(P, "P")
+    if eta is not None:
+        _series_check(eta, "eta")
+    R = U.shape[0]
+    p = _prec(precision)
+    need = nat.lib().nspt_workspace_size(R, ctypes.byref(params), p)
+    if need == 0:
+        raise ValueError("invalid NSPT parameters")
+    if ws is None:
+        ws = workspace(need, U.device)
+    st = nat.lib().nspt_md_trajectory(U.data_ptr(), P.data_ptr(), None if eta is None else eta.data_ptr(), R,
+                                      ctypes.byref(params), int(nsteps), p, ws.data_ptr(), ws.numel(),
+                                      _stream_ptr(U.device))
+    nat.check(st, "nspt_md_trajectory")
+    return U, P
+
+
 def timing_enable(on: bool = True) -> None:
     """Bracket every library launch with HIP events (for measurement only)."""
     nat.check(nat.lib().polymat_timing_enable(1 if on else 0), "polymat_timing_enable")

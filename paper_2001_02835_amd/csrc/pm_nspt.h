@@ -1,4 +1,4 @@
-// Internal interface of the NSPT Euler-Langevin step (pm_nspt.hip).
+// Internal interface of the NSPT updates (pm_nspt.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,5 +11,7 @@ namespace pm {
 size_t nspt_workspace_bytes(int replicas, const nspt_params* params, int precision);
 pm_status nspt_step(void* U, const void* eta, int replicas, const nspt_params* params, int precision,
                     void* workspace, size_t workspace_bytes, hipStream_t stream);
+pm_status nspt_md(void* U, void* P, const void* eta, int replicas, const nspt_params* params, int nsteps,
+                  int precision, void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 }  // namespace pm

@@ -1,10 +1,15 @@
-// Host orchestration of one NSPT Euler-Langevin step of the TEK model
-// (eqs. (1)-(3)) for R replicas at once, on the FFT-CONV building blocks.
+// Host orchestration of the NSPT updates of the TEK model (eqs. (1)-(3)) for
+// R replicas at once, on the FFT-CONV building blocks: one Euler-Langevin
+// step, and one leapfrog trajectory of the molecular-dynamics form of the
+// tower (the integrator the paper names below eq. (3)).
 //
-// One rescale factor s is chosen per call from the per-order norms of all
-// link series; every series of the step then lives in the rescaled variable
-// (order k multiplied by s^k), which keeps all Fourier-space products
-// consistent with each other.  With U~ the transforms of the old links:
+// Two rescale factors are chosen on the device per update: s from the
+// per-order norms of all link series for the staple products, and s' from the
+// norms of the exponent Y and of the links for the exponential and the link
+// update (Y can grow much faster with the order than U).  Within each group
+// every series lives in the rescaled variable (order k multiplied by s^k),
+// which keeps its Fourier-space products consistent with each other.  With
+// U~ the transforms of the links:
 //
 //  staples (42 products per replica, 24 re-truncations)
 //    Q_mn = U_m * U_n           (m != n)      R_mn = U_m * U_n^+   (m < n)
@@ -15,8 +20,9 @@
 //    S_n are conjugate to each other, so D_m = M_m - M_m^+ with
 //    M_m = sum_{n>m} z_mn P_mn - sum_{n<m} z_nm P_nm + sum_{n!=m} z_mn^* T_mn,
 //    formed in Fourier space and transformed back once per direction.
-//  drift and noise
-//    Y_m = i X_m = -eps (D - Tr D / N) + i sqrt(2 eps) eta_m g,  Y^(0) = 0
+//  exponent Y (then rescaled by s'^k)
+//    Langevin:  Y_m = i X_m = -eps (D - Tr D / N) + i sqrt(2 eps) eta_m g,  Y^(0) = 0
+//    MD:        P^(k) += c F^(k) (k >= 1, F = i (D - Tr D / N)), then Y = i dt P
 //  exponential, Paterson-Stockmeyer with block b ~ sqrt(ntrunc + 1)
 //    Y^2..Y^b by products; E = sum_q (Y^b)^q B_q(Y), B_q = sum_{i<b} Y^i / (qb + i)!
 //    by Horner in Y^b; B_q is added inside the re-truncation of each link.
@@ -65,7 +71,7 @@ FourierType out_type(int prec) { return prec == PM_PREC_FP64 ? kF64 : kF32; }
 struct Layout {
   int n, E, nord, L, R, b;
   size_t fin, fout, tser;        // bytes: Fourier (product input), Fourier (product output), time series
-  size_t rec, unit, part, trc;   // small tables
+  size_t rec, rec2, unit, part, partY, trc;   // small tables
   size_t Ut, G, Xt, M, Ypt, Ypf, Z;
   size_t total;
 };
@@ -86,8 +92,10 @@ Layout layout(int R, const nspt_params* p, int prec) {
   l.tser = align_up(E * l.nord * 16);
   size_t off = 0;
   l.rec = off;  off += align_up(sizeof(ScaleRec));
+  l.rec2 = off; off += align_up(sizeof(ScaleRec));
   l.unit = off; off += align_up(sizeof(ScaleRec));
   l.part = off; off += align_up(static_cast<size_t>(4) * R * l.nord * kNormChunks * sizeof(double));
+  l.partY = off; off += align_up(static_cast<size_t>(4) * R * l.nord * kNormChunks * sizeof(double));
   l.trc = off;  off += align_up(static_cast<size_t>(4) * R * l.nord * 16);
   l.Ut = off;   off += static_cast<size_t>(4) * R * l.fin;
   l.G = off;    off += static_cast<size_t>(24) * R * l.fout;
@@ -171,57 +179,39 @@ struct RetruncBatch {
 
 }  // namespace
 
-size_t nspt_workspace_bytes(int replicas, const nspt_params* p, int prec) {
-  if (!valid_params(replicas, p, prec)) return 0;
-  return layout(replicas, p, prec).total;
-}
+namespace {
 
-pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int prec, void* workspace,
-                    size_t workspace_bytes, hipStream_t s) {
-  if (!valid_params(R, p, prec)) return PM_ERR_INVALID;
-  if (!U || !eta || !workspace) return PM_ERR_INVALID;
-  if (reinterpret_cast<uintptr_t>(U) % 16 || reinterpret_cast<uintptr_t>(eta) % 16 ||
-      reinterpret_cast<uintptr_t>(workspace) % kAlign)
-    return PM_ERR_INVALID;
-  const Layout l = layout(R, p, prec);
-  if (workspace_bytes < l.total) return PM_ERR_WORKSPACE;
-  {
-    const uintptr_t wb = reinterpret_cast<uintptr_t>(workspace), we = wb + l.total;
-    const uintptr_t ub = reinterpret_cast<uintptr_t>(U), ue = ub + static_cast<size_t>(R) * 4 * l.nord * l.E * 16;
-    const uintptr_t nb = reinterpret_cast<uintptr_t>(eta), ne = nb + static_cast<size_t>(R) * 4 * l.E * 16;
-    if ((wb < ue && ub < we) || (wb < ne && nb < we) || (ub < ne && nb < ue)) return PM_ERR_INVALID;
-  }
-
-  char* ws = static_cast<char*>(workspace);
-  const FourierType fin = in_type(prec), fout = out_type(prec);
-  const int n = l.n, E = l.E, nord = l.nord, L = l.L, b = l.b;
-  ScaleRec* rec = reinterpret_cast<ScaleRec*>(ws + l.rec);
-  ScaleRec* unit = reinterpret_cast<ScaleRec*>(ws + l.unit);
-  double* part = reinterpret_cast<double*>(ws + l.part);
-  double2* trc = reinterpret_cast<double2*>(ws + l.trc);
-  double2* Ug = static_cast<double2*>(U);
-  const double2* etag = static_cast<const double2*>(eta);
-  const size_t series_elems = static_cast<size_t>(nord) * E;
-
-  auto Useries = [&](int r, int mu) { return Ug + (static_cast<size_t>(r) * 4 + mu) * series_elems; };
-  auto Ut = [&](int r, int mu) { return ws + l.Ut + (static_cast<size_t>(r) * 4 + mu) * l.fin; };
-  auto G = [&](int r, int slot) { return ws + l.G + (static_cast<size_t>(r) * 24 + slot) * l.fout; };
-  auto Xt = [&](int r, int slot) { return ws + l.Xt + (static_cast<size_t>(r) * 24 + slot) * l.fin; };
-  auto Mser = [&](int r, int mu) {
-    return reinterpret_cast<double2*>(ws + l.M + (static_cast<size_t>(r) * 4 + mu) * l.tser);
-  };
-  // powers Y^j, j = 1..b, slot j - 1
-  auto Ypt = [&](int r, int mu, int j) {
-    return reinterpret_cast<double2*>(ws + l.Ypt + ((static_cast<size_t>(r) * 4 + mu) * b + (j - 1)) * l.tser);
-  };
-  auto Ypf = [&](int r, int mu, int j) {
-    return ws + l.Ypf + ((static_cast<size_t>(r) * 4 + mu) * b + (j - 1)) * l.fin;
-  };
-  auto Zf = [&](int r, int mu) { return ws + l.Z + (static_cast<size_t>(r) * 4 + mu) * l.fin; };
-
-  // slot maps: Q_mn (m != n) -> 0..11, R_mn (m < n) -> 12..17, W_mn (m < n) -> 18..23
+// One call's view of the workspace and the stages of a force evaluation and
+// link update.  Every stage enqueues on `s` and returns the first error.
+struct Run {
+  Layout l;
+  const nspt_params* p;
+  int R, prec;
+  FourierType fin, fout;
+  hipStream_t s;
+  char* ws;
+  double2* Ug;
+  ScaleRec* rec;
+  ScaleRec* rec2;
+  ScaleRec* unit;
+  double* part;
+  double* partY;
+  double2* trc;
+  size_t series_elems;
   int qslot[4][4], pair[4][4];
-  {
+
+  Run(void* U, int R_, const nspt_params* p_, int prec_, void* workspace, hipStream_t s_)
+      : l(layout(R_, p_, prec_)), p(p_), R(R_), prec(prec_), fin(in_type(prec_)), fout(out_type(prec_)), s(s_) {
+    ws = static_cast<char*>(workspace);
+    Ug = static_cast<double2*>(U);
+    rec = reinterpret_cast<ScaleRec*>(ws + l.rec);
+    rec2 = reinterpret_cast<ScaleRec*>(ws + l.rec2);
+    unit = reinterpret_cast<ScaleRec*>(ws + l.unit);
+    part = reinterpret_cast<double*>(ws + l.part);
+    partY = reinterpret_cast<double*>(ws + l.partY);
+    trc = reinterpret_cast<double2*>(ws + l.trc);
+    series_elems = static_cast<size_t>(l.nord) * l.E;
+    // slot maps: Q_mn (m != n) -> 0..11, R_mn (m < n) -> 12..17, W_mn (m < n) -> 18..23
     int q = 0, pr = 0;
     for (int m = 0; m < 4; ++m)
       for (int nn = 0; nn < 4; ++nn) {
@@ -230,8 +220,26 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
       }
   }
 
-  // ---- 1. rescale factor from the norms of all link series; unit record
-  {
+  double2* Useries(int r, int mu) const { return Ug + (static_cast<size_t>(r) * 4 + mu) * series_elems; }
+  char* Ut(int r, int mu) const { return ws + l.Ut + (static_cast<size_t>(r) * 4 + mu) * l.fin; }
+  char* G(int r, int slot) const { return ws + l.G + (static_cast<size_t>(r) * 24 + slot) * l.fout; }
+  char* Xt(int r, int slot) const { return ws + l.Xt + (static_cast<size_t>(r) * 24 + slot) * l.fin; }
+  double2* Mser(int r, int mu) const {
+    return reinterpret_cast<double2*>(ws + l.M + (static_cast<size_t>(r) * 4 + mu) * l.tser);
+  }
+  // powers Y^j, j = 1..b, slot j - 1
+  double2* Ypt(int r, int mu, int j) const {
+    return reinterpret_cast<double2*>(ws + l.Ypt + ((static_cast<size_t>(r) * 4 + mu) * l.b + (j - 1)) * l.tser);
+  }
+  char* Ypf(int r, int mu, int j) const {
+    return ws + l.Ypf + ((static_cast<size_t>(r) * 4 + mu) * l.b + (j - 1)) * l.fin;
+  }
+  char* Zf(int r, int mu) const { return ws + l.Z + (static_cast<size_t>(r) * 4 + mu) * l.fin; }
+
+  // ---- rescale factor from the norms of all link series (and the unit
+  //      record), then the forward transforms of the links
+  pm_status links_forward() {
+    const int E = l.E, nord = l.nord, L = l.L, n = l.n;
     NormArgs na{};
     for (int r = 0; r < R; ++r)
       for (int mu = 0; mu < 4; ++mu) {
@@ -263,15 +271,12 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
     sa.jobs[1].nser = 1;
     e = st(timed(PM_PHASE_RESCALE, s, [&] { return launch_scale(sa, s); }));
     if (e) return e;
-  }
 
-  // ---- 2. forward transforms of the links
-  {
     FwdArgs fa{};
     for (int r = 0; r < R; ++r)
       for (int mu = 0; mu < 4; ++mu) {
         if (fa.njobs == kMaxTransformJobs) {
-          pm_status e = st(timed(PM_PHASE_FORWARD, s, [&] { return launch_forward(fa, L, E, fin, s); }));
+          e = st(timed(PM_PHASE_FORWARD, s, [&] { return launch_forward(fa, L, E, fin, s); }));
           if (e) return e;
           fa.njobs = 0;
         }
@@ -283,96 +288,95 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
         j.nord = nord;
         j.n = n;
       }
-    pm_status e = st(timed(PM_PHASE_FORWARD, s, [&] { return launch_forward(fa, L, E, fin, s); }));
-    if (e) return e;
+    return st(timed(PM_PHASE_FORWARD, s, [&] { return launch_forward(fa, L, E, fin, s); }));
   }
 
-  // ---- 3. first staple wave: Q, R, W
-  {
-    GemmBatch nn{fin, s, 0}, nc{fin, s, 1}, cn{fin, s, 2};
-    for (int r = 0; r < R; ++r)
-      for (int m = 0; m < 4; ++m)
-        for (int q = 0; q < 4; ++q) {
-          if (m == q) continue;
-          nn.add(Ut(r, m), Ut(r, q), G(r, qslot[m][q]), n, L);
-          if (m < q) {
-            nc.add(Ut(r, m), Ut(r, q), G(r, 12 + pair[m][q]), n, L);
-            cn.add(Ut(r, m), Ut(r, q), G(r, 18 + pair[m][q]), n, L);
+  // ---- staples: M_m of every replica and direction (unscaled time domain)
+  //      and the traces Tr M^(k)
+  pm_status staples() {
+    const int n = l.n, E = l.E, nord = l.nord, L = l.L;
+    // first wave: Q, R, W, re-truncated in Fourier space
+    {
+      GemmBatch nn{fin, s, 0}, nc{fin, s, 1}, cn{fin, s, 2};
+      for (int r = 0; r < R; ++r)
+        for (int m = 0; m < 4; ++m)
+          for (int q = 0; q < 4; ++q) {
+            if (m == q) continue;
+            nn.add(Ut(r, m), Ut(r, q), G(r, qslot[m][q]), n, L);
+            if (m < q) {
+              nc.add(Ut(r, m), Ut(r, q), G(r, 12 + pair[m][q]), n, L);
+              cn.add(Ut(r, m), Ut(r, q), G(r, 18 + pair[m][q]), n, L);
+            }
           }
-        }
-    nn.flush();
-    nc.flush();
-    cn.flush();
-    if (nn.status || nc.status || cn.status) return PM_ERR_DEVICE;
-    RetruncBatch rt{&l, fout, fin, s};
-    rt.a.nadd = 0;
-    rt.a.idcoef = make_double2(0.0, 0.0);
-    for (int r = 0; r < R; ++r)
-      for (int slot = 0; slot < 24; ++slot) rt.add(G(r, slot), Xt(r, slot), nullptr, nullptr, 0);
-    rt.flush();
-    if (rt.status) return rt.status;
-  }
-
-  // ---- 4. second staple wave: P (6) into G slots 0..5, T (12) into G slots 6..17
-  {
-    GemmBatch nc{fin, s, 1}, nn{fin, s, 0}, cc{fin, s, 3};
-    for (int r = 0; r < R; ++r)
-      for (int m = 0; m < 4; ++m)
-        for (int q = 0; q < 4; ++q) {
-          if (m == q) continue;
-          if (m < q) {
-            nc.add(Xt(r, qslot[m][q]), Xt(r, qslot[q][m]), G(r, pair[m][q]), n, L);          // P_mq
-            nn.add(Xt(r, 12 + pair[m][q]), Xt(r, 18 + pair[m][q]), G(r, 6 + qslot[m][q]), n, L);  // T_mq
-          } else {
-            cc.add(Xt(r, 12 + pair[q][m]), Xt(r, 18 + pair[q][m]), G(r, 6 + qslot[m][q]), n, L);  // T_mq, m > q
+      nn.flush();
+      nc.flush();
+      cn.flush();
+      if (nn.status || nc.status || cn.status) return PM_ERR_DEVICE;
+      RetruncBatch rt{&l, fout, fin, s};
+      rt.a.nadd = 0;
+      rt.a.idcoef = make_double2(0.0, 0.0);
+      for (int r = 0; r < R; ++r)
+        for (int slot = 0; slot < 24; ++slot) rt.add(G(r, slot), Xt(r, slot), nullptr, nullptr, 0);
+      rt.flush();
+      if (rt.status) return rt.status;
+    }
+    // second wave: P (6) into G slots 0..5, T (12) into G slots 6..17
+    {
+      GemmBatch nc{fin, s, 1}, nn{fin, s, 0}, cc{fin, s, 3};
+      for (int r = 0; r < R; ++r)
+        for (int m = 0; m < 4; ++m)
+          for (int q = 0; q < 4; ++q) {
+            if (m == q) continue;
+            if (m < q) {
+              nc.add(Xt(r, qslot[m][q]), Xt(r, qslot[q][m]), G(r, pair[m][q]), n, L);               // P_mq
+              nn.add(Xt(r, 12 + pair[m][q]), Xt(r, 18 + pair[m][q]), G(r, 6 + qslot[m][q]), n, L);  // T_mq
+            } else {
+              cc.add(Xt(r, 12 + pair[q][m]), Xt(r, 18 + pair[q][m]), G(r, 6 + qslot[m][q]), n, L);  // T_mq, m > q
+            }
           }
-        }
-    nc.flush();
-    nn.flush();
-    cc.flush();
-    if (nn.status || nc.status || cc.status) return PM_ERR_DEVICE;
-  }
-
-  // ---- 5. M_m: weighted sum of P and T, back to the (unscaled) time domain
-  {
-    CombineArgs ca{};
-    auto flush = [&]() -> pm_status {
-      if (ca.njobs == 0) return PM_OK;
-      pm_status e = st(timed(PM_PHASE_INVERSE, s, [&] { return launch_inv_combine(ca, L, E, fout, s); }));
-      ca.njobs = 0;
-      return e;
-    };
-    for (int r = 0; r < R; ++r)
-      for (int m = 0; m < 4; ++m) {
-        if (ca.njobs == kMaxCombineJobs) { pm_status e = flush(); if (e) return e; }
-        CombineJob& j = ca.jobs[ca.njobs++];
-        j.nsrc = 0;
-        for (int q = 0; q < 4; ++q) {
-          if (q == m) continue;
-          if (q > m) {
-            j.src[j.nsrc] = G(r, pair[m][q]);
-            j.coef[j.nsrc++] = twist(p, m, q);
-          } else {
-            const double2 z = twist(p, q, m);
-            j.src[j.nsrc] = G(r, pair[q][m]);
-            j.coef[j.nsrc++] = make_double2(-z.x, -z.y);
+      nc.flush();
+      nn.flush();
+      cc.flush();
+      if (nn.status || nc.status || cc.status) return PM_ERR_DEVICE;
+    }
+    // M_m: weighted sum of P and T, back to the (unscaled) time domain
+    {
+      CombineArgs ca{};
+      auto flush = [&]() -> pm_status {
+        if (ca.njobs == 0) return PM_OK;
+        pm_status e = st(timed(PM_PHASE_INVERSE, s, [&] { return launch_inv_combine(ca, L, E, fout, s); }));
+        ca.njobs = 0;
+        return e;
+      };
+      for (int r = 0; r < R; ++r)
+        for (int m = 0; m < 4; ++m) {
+          if (ca.njobs == kMaxCombineJobs) { pm_status e = flush(); if (e) return e; }
+          CombineJob& j = ca.jobs[ca.njobs++];
+          j.nsrc = 0;
+          for (int q = 0; q < 4; ++q) {
+            if (q == m) continue;
+            if (q > m) {
+              j.src[j.nsrc] = G(r, pair[m][q]);
+              j.coef[j.nsrc++] = twist(p, m, q);
+            } else {
+              const double2 z = twist(p, q, m);
+              j.src[j.nsrc] = G(r, pair[q][m]);
+              j.coef[j.nsrc++] = make_double2(-z.x, -z.y);
+            }
+            const double2 z = twist(p, m, q);
+            j.src[j.nsrc] = G(r, 6 + qslot[m][q]);
+            j.coef[j.nsrc++] = make_double2(z.x, -z.y);
           }
-          const double2 z = twist(p, m, q);
-          j.src[j.nsrc] = G(r, 6 + qslot[m][q]);
-          j.coef[j.nsrc++] = make_double2(z.x, -z.y);
+          j.dst = Mser(r, m);
+          j.rec = rec;
+          j.E = E;
+          j.nord = nord;
+          j.kmin = 0;
         }
-        j.dst = Mser(r, m);
-        j.rec = rec;
-        j.E = E;
-        j.nord = nord;
-        j.kmin = 0;
-      }
-    pm_status e = flush();
-    if (e) return e;
-  }
-
-  // ---- 6. traces and the drift-plus-noise exponent Y (scaled), Y^1 = Y
-  {
+      pm_status e = flush();
+      if (e) return e;
+    }
+    // traces
     TraceArgs ta{};
     for (int r = 0; r < R; ++r)
       for (int m = 0; m < 4; ++m) {
@@ -387,127 +391,291 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
         j.n = n;
         j.nord = nord;
       }
-    pm_status e = st(timed(PM_PHASE_OTHER, s, [&] { return launch_trace(ta, nord, s); }));
-    if (e) return e;
+    return st(timed(PM_PHASE_OTHER, s, [&] { return launch_trace(ta, nord, s); }));
+  }
+
+  // ---- force pass.  Langevin (P == nullptr): Y^1 = i X from the force and
+  //      the noise.  MD: P^(k) += kick F^(k) (k >= 1) and, when write_y,
+  //      Y^1 = i dt P (unscaled).
+  pm_status force(const double2* eta, double2* P, double kick, double dt, bool write_y) {
+    const int n = l.n, nord = l.nord;
     ForceArgs fa{};
+    fa.md = P ? 1 : 0;
     fa.eps = p->eps;
     fa.noise_amp = std::sqrt(2.0 * p->eps);
+    fa.kick = kick;
+    fa.dt = dt;
     for (int r = 0; r < R; ++r)
       for (int m = 0; m < 4; ++m) {
         if (fa.njobs == kMaxForceJobs) {
-          e = st(timed(PM_PHASE_OTHER, s, [&] { return launch_force(fa, n, nord, s); }));
+          pm_status e = st(timed(PM_PHASE_OTHER, s, [&] { return launch_force(fa, n, nord, s); }));
           if (e) return e;
           fa.njobs = 0;
         }
         ForceJob& j = fa.jobs[fa.njobs++];
         j.M = Mser(r, m);
         j.tr = trc + (static_cast<size_t>(r) * 4 + m) * nord;
-        j.eta = etag + (static_cast<size_t>(r) * 4 + m) * E;
-        j.Y = Ypt(r, m, 1);
-        j.rec = rec;
+        j.eta = eta ? eta + (static_cast<size_t>(r) * 4 + m) * l.E : nullptr;
+        j.P = P ? P + (static_cast<size_t>(r) * 4 + m) * series_elems : nullptr;
+        j.Y = write_y ? Ypt(r, m, 1) : nullptr;
+        j.rec = unit;                  // Y unscaled; rescaled by s' before the exponential
         j.n = n;
         j.nord = nord;
       }
-    e = st(timed(PM_PHASE_OTHER, s, [&] { return launch_force(fa, n, nord, s); }));
-    if (e) return e;
-    // Fourier coefficients of Y (already scaled: unit record)
-    FwdArgs fw{};
-    for (int r = 0; r < R; ++r)
-      for (int m = 0; m < 4; ++m) {
-        if (fw.njobs == kMaxTransformJobs) {
-          e = st(timed(PM_PHASE_FORWARD, s, [&] { return launch_forward(fw, L, E, fin, s); }));
-          if (e) return e;
-          fw.njobs = 0;
-        }
-        FwdJob& j = fw.jobs[fw.njobs++];
-        j.src = Ypt(r, m, 1);
-        j.dst = Ypf(r, m, 1);
-        j.rec = unit;
-        j.E = E;
-        j.nord = nord;
-        j.n = n;
-      }
-    e = st(timed(PM_PHASE_FORWARD, s, [&] { return launch_forward(fw, L, E, fin, s); }));
-    if (e) return e;
+    return st(timed(PM_PHASE_OTHER, s, [&] { return launch_force(fa, n, nord, s); }));
   }
 
-  // ---- 7. powers Y^2 .. Y^b
-  for (int j = 2; j <= b; ++j) {
-    GemmBatch g{fin, s, 0};
-    for (int r = 0; r < R; ++r)
-      for (int m = 0; m < 4; ++m) g.add(Ypf(r, m, j - 1), Ypf(r, m, 1), G(r, m), n, L);
-    g.flush();
-    if (g.status) return g.status;
-    RetruncBatch rt{&l, fout, fin, s};
-    rt.a.nadd = 0;
-    rt.a.idcoef = make_double2(0.0, 0.0);
-    for (int r = 0; r < R; ++r)
-      for (int m = 0; m < 4; ++m) rt.add(G(r, m), Ypf(r, m, j), Ypt(r, m, j), nullptr, 0);
-    rt.flush();
-    if (rt.status) return rt.status;
-  }
-
-  // ---- 8. E = sum_q (Y^b)^q B_q(Y) by Horner in Y^b
-  {
-    const int nt = nord - 1;
-    const int Q = nt / b;
-    auto cfac = [&](int jj) {
-      if (jj > nt) return 0.0;
-      double f = 1.0;
-      for (int t = 2; t <= jj; ++t) f *= t;
-      return 1.0 / f;
-    };
-    const size_t ystride = l.tser / sizeof(double2);   // elements between Y^i and Y^(i+1)
-    for (int q = Q; q >= 0; --q) {
-      if (q < Q) {
-        GemmBatch g{fin, s, 0};
-        for (int r = 0; r < R; ++r)
-          for (int m = 0; m < 4; ++m) g.add(Ypf(r, m, b), Zf(r, m), G(r, m), n, L);
-        g.flush();
-        if (g.status) return g.status;
-      }
-      RetruncBatch rt{&l, fout, fin, s};
-      rt.a.nadd = b - 1;
-      for (int i = 1; i < b; ++i) rt.a.coef[i - 1] = make_double2(cfac(q * b + i), 0.0);
-      rt.a.idcoef = make_double2(cfac(q * b), 0.0);
+  // ---- exponential of Y (Y^1 in Ypt(.,.,1), scaled) into Zf, then the link
+  //      update U_m <- E_m * U_m (orders >= 1)
+  pm_status exp_and_update() {
+    const int n = l.n, E = l.E, nord = l.nord, L = l.L, b = l.b;
+    // s' from the norms of Y (all replicas and directions) against those of
+    // the links, then Y <- Y(s' g) in place
+    {
+      NormArgs na{};
+      auto flush = [&]() -> pm_status {
+        pm_status e = st(timed(PM_PHASE_RESCALE, s, [&] { return launch_norms(na, nord, s); }));
+        na.njobs = 0;
+        return e;
+      };
       for (int r = 0; r < R; ++r)
-        for (int m = 0; m < 4; ++m)
-          rt.add(q < Q ? static_cast<const void*>(G(r, m)) : nullptr, Zf(r, m), nullptr,
-                 b > 1 ? Ypt(r, m, 1) : nullptr, ystride);
+        for (int mu = 0; mu < 4; ++mu) {
+          if (na.njobs == kMaxTransformJobs) { pm_status e = flush(); if (e) return e; }
+          NormJob& j = na.jobs[na.njobs++];
+          j.src = Ypt(r, mu, 1);
+          j.partial = partY + (static_cast<size_t>(r) * 4 + mu) * nord * kNormChunks;
+          j.E = E;
+          j.nord = nord;
+        }
+      pm_status e = flush();
+      if (e) return e;
+      ScaleArgs sa{};
+      sa.njobs = 1;
+      sa.jobs[0].partA = partY;
+      sa.jobs[0].partB = part;
+      sa.jobs[0].rec = rec2;
+      sa.jobs[0].nord = nord;
+      sa.jobs[0].L = L;
+      sa.jobs[0].fixed_s = 0.0;
+      sa.jobs[0].nser = 4 * R;
+      e = st(timed(PM_PHASE_RESCALE, s, [&] { return launch_scale(sa, s); }));
+      if (e) return e;
+      SeriesScaleArgs ss{};
+      auto flush2 = [&]() -> pm_status {
+        pm_status e2 = st(timed(PM_PHASE_OTHER, s, [&] { return launch_series_scale(ss, nord, s); }));
+        ss.njobs = 0;
+        return e2;
+      };
+      for (int r = 0; r < R; ++r)
+        for (int mu = 0; mu < 4; ++mu) {
+          if (ss.njobs == kMaxSeriesScaleJobs) { e = flush2(); if (e) return e; }
+          SeriesScaleJob& j = ss.jobs[ss.njobs++];
+          j.x = Ypt(r, mu, 1);
+          j.rec = rec2;
+          j.E = E;
+          j.nord = nord;
+        }
+      e = flush2();
+      if (e) return e;
+    }
+    // Fourier coefficients of Y (already scaled: unit record)
+    {
+      FwdArgs fw{};
+      for (int r = 0; r < R; ++r)
+        for (int m = 0; m < 4; ++m) {
+          if (fw.njobs == kMaxTransformJobs) {
+            pm_status e = st(timed(PM_PHASE_FORWARD, s, [&] { return launch_forward(fw, L, E, fin, s); }));
+            if (e) return e;
+            fw.njobs = 0;
+          }
+          FwdJob& j = fw.jobs[fw.njobs++];
+          j.src = Ypt(r, m, 1);
+          j.dst = Ypf(r, m, 1);
+          j.rec = unit;
+          j.E = E;
+          j.nord = nord;
+          j.n = n;
+        }
+      pm_status e = st(timed(PM_PHASE_FORWARD, s, [&] { return launch_forward(fw, L, E, fin, s); }));
+      if (e) return e;
+    }
+    // powers Y^2 .. Y^b
+    for (int j = 2; j <= b; ++j) {
+      GemmBatch g{fin, s, 0};
+      for (int r = 0; r < R; ++r)
+        for (int m = 0; m < 4; ++m) g.add(Ypf(r, m, j - 1), Ypf(r, m, 1), G(r, m), n, L);
+      g.flush();
+      if (g.status) return g.status;
+      RetruncBatch rt{&l, fout, fin, s};
+      rt.a.nadd = 0;
+      rt.a.idcoef = make_double2(0.0, 0.0);
+      for (int r = 0; r < R; ++r)
+        for (int m = 0; m < 4; ++m) rt.add(G(r, m), Ypf(r, m, j), Ypt(r, m, j), nullptr, 0);
       rt.flush();
       if (rt.status) return rt.status;
     }
+    // E = sum_q (Y^b)^q B_q(Y) by Horner in Y^b
+    {
+      const int nt = nord - 1;
+      const int Q = nt / b;
+      auto cfac = [&](int jj) {
+        if (jj > nt) return 0.0;
+        double f = 1.0;
+        for (int t = 2; t <= jj; ++t) f *= t;
+        return 1.0 / f;
+      };
+      const size_t ystride = l.tser / sizeof(double2);   // elements between Y^i and Y^(i+1)
+      for (int q = Q; q >= 0; --q) {
+        if (q < Q) {
+          GemmBatch g{fin, s, 0};
+          for (int r = 0; r < R; ++r)
+            for (int m = 0; m < 4; ++m) g.add(Ypf(r, m, b), Zf(r, m), G(r, m), n, L);
+          g.flush();
+          if (g.status) return g.status;
+        }
+        RetruncBatch rt{&l, fout, fin, s};
+        rt.a.nadd = b - 1;
+        for (int i = 1; i < b; ++i) rt.a.coef[i - 1] = make_double2(cfac(q * b + i), 0.0);
+        rt.a.idcoef = make_double2(cfac(q * b), 0.0);
+        for (int r = 0; r < R; ++r)
+          for (int m = 0; m < 4; ++m)
+            rt.add(q < Q ? static_cast<const void*>(G(r, m)) : nullptr, Zf(r, m), nullptr,
+                   b > 1 ? Ypt(r, m, 1) : nullptr, ystride);
+        rt.flush();
+        if (rt.status) return rt.status;
+      }
+    }
+    // link update U_m <- E_m * U_m (orders >= 1), with U transformed again
+    // in the variable s'
+    {
+      FwdArgs fa{};
+      for (int r = 0; r < R; ++r)
+        for (int mu = 0; mu < 4; ++mu) {
+          if (fa.njobs == kMaxTransformJobs) {
+            pm_status e = st(timed(PM_PHASE_FORWARD, s, [&] { return launch_forward(fa, L, E, fin, s); }));
+            if (e) return e;
+            fa.njobs = 0;
+          }
+          FwdJob& j = fa.jobs[fa.njobs++];
+          j.src = Useries(r, mu);
+          j.dst = Ut(r, mu);
+          j.rec = rec2;
+          j.E = E;
+          j.nord = nord;
+          j.n = n;
+        }
+      pm_status e = st(timed(PM_PHASE_FORWARD, s, [&] { return launch_forward(fa, L, E, fin, s); }));
+      if (e) return e;
+      GemmBatch g{fin, s, 0};
+      for (int r = 0; r < R; ++r)
+        for (int m = 0; m < 4; ++m) g.add(Zf(r, m), Ut(r, m), G(r, m), n, L);
+      g.flush();
+      if (g.status) return g.status;
+      CombineArgs ca{};
+      for (int r = 0; r < R; ++r)
+        for (int m = 0; m < 4; ++m) {
+          if (ca.njobs == kMaxCombineJobs) {
+            pm_status e = st(timed(PM_PHASE_INVERSE, s, [&] { return launch_inv_combine(ca, L, E, fout, s); }));
+            if (e) return e;
+            ca.njobs = 0;
+          }
+          CombineJob& j = ca.jobs[ca.njobs++];
+          j.nsrc = 1;
+          j.src[0] = G(r, m);
+          j.coef[0] = make_double2(1.0, 0.0);
+          j.dst = Useries(r, m);
+          j.rec = rec2;
+          j.E = E;
+          j.nord = nord;
+          j.kmin = 1;
+        }
+      return st(timed(PM_PHASE_INVERSE, s, [&] { return launch_inv_combine(ca, L, E, fout, s); }));
+    }
   }
+};
 
-  // ---- 9. link update U_m <- E_m * U_m (orders >= 1)
-  {
-    GemmBatch g{fin, s, 0};
-    for (int r = 0; r < R; ++r)
-      for (int m = 0; m < 4; ++m) g.add(Zf(r, m), Ut(r, m), G(r, m), n, L);
-    g.flush();
-    if (g.status) return g.status;
-    CombineArgs ca{};
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t ab = reinterpret_cast<uintptr_t>(a), bb = reinterpret_cast<uintptr_t>(b);
+  return ab < bb + nb && bb < ab + na;
+}
+
+}  // namespace
+
+size_t nspt_workspace_bytes(int replicas, const nspt_params* p, int prec) {
+  if (!valid_params(replicas, p, prec)) return 0;
+  return layout(replicas, p, prec).total;
+}
+
+pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int prec, void* workspace,
+                    size_t workspace_bytes, hipStream_t s) {
+  if (!valid_params(R, p, prec)) return PM_ERR_INVALID;
+  if (!U || !eta || !workspace) return PM_ERR_INVALID;
+  if (reinterpret_cast<uintptr_t>(U) % 16 || reinterpret_cast<uintptr_t>(eta) % 16 ||
+      reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return PM_ERR_INVALID;
+  const Layout l = layout(R, p, prec);
+  if (workspace_bytes < l.total) return PM_ERR_WORKSPACE;
+  const size_t ub = static_cast<size_t>(R) * 4 * l.nord * l.E * 16, nb = static_cast<size_t>(R) * 4 * l.E * 16;
+  if (overlaps(workspace, l.total, U, ub) || overlaps(workspace, l.total, eta, nb) || overlaps(U, ub, eta, nb))
+    return PM_ERR_INVALID;
+
+  Run run(U, R, p, prec, workspace, s);
+  pm_status e = run.links_forward();
+  if (!e) e = run.staples();
+  if (!e) e = run.force(static_cast<const double2*>(eta), nullptr, 0.0, 0.0, true);
+  if (!e) e = run.exp_and_update();
+  return e;
+}
+
+pm_status nspt_md(void* U, void* P, const void* eta, int R, const nspt_params* p, int nsteps, int prec,
+                  void* workspace, size_t workspace_bytes, hipStream_t s) {
+  if (!valid_params(R, p, prec)) return PM_ERR_INVALID;
+  if (!U || !P || !workspace || nsteps < 1 || nsteps > kMaxMdSteps) return PM_ERR_INVALID;
+  if (reinterpret_cast<uintptr_t>(U) % 16 || reinterpret_cast<uintptr_t>(P) % 16 ||
+      reinterpret_cast<uintptr_t>(eta) % 16 || reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return PM_ERR_INVALID;
+  const Layout l = layout(R, p, prec);
+  if (workspace_bytes < l.total) return PM_ERR_WORKSPACE;
+  const size_t ub = static_cast<size_t>(R) * 4 * l.nord * l.E * 16, nb = static_cast<size_t>(R) * 4 * l.E * 16;
+  if (overlaps(workspace, l.total, U, ub) || overlaps(workspace, l.total, P, ub) || overlaps(U, ub, P, ub))
+    return PM_ERR_INVALID;
+  if (eta && (overlaps(workspace, l.total, eta, nb) || overlaps(U, ub, eta, nb) || overlaps(P, ub, eta, nb)))
+    return PM_ERR_INVALID;
+
+  double2* Pg = static_cast<double2*>(P);
+  if (eta) {
+    RefreshArgs ra{};
     for (int r = 0; r < R; ++r)
       for (int m = 0; m < 4; ++m) {
-        if (ca.njobs == kMaxCombineJobs) {
-          pm_status e = st(timed(PM_PHASE_INVERSE, s, [&] { return launch_inv_combine(ca, L, E, fout, s); }));
+        if (ra.njobs == kMaxRefreshJobs) {
+          pm_status e = st(timed(PM_PHASE_OTHER, s, [&] { return launch_refresh(ra, s); }));
           if (e) return e;
-          ca.njobs = 0;
+          ra.njobs = 0;
         }
-        CombineJob& j = ca.jobs[ca.njobs++];
-        j.nsrc = 1;
-        j.src[0] = G(r, m);
-        j.coef[0] = make_double2(1.0, 0.0);
-        j.dst = Useries(r, m);
-        j.rec = rec;
-        j.E = E;
-        j.nord = nord;
-        j.kmin = 1;
+        RefreshJob& j = ra.jobs[ra.njobs++];
+        j.P = Pg + (static_cast<size_t>(r) * 4 + m) * l.nord * l.E;
+        j.eta = static_cast<const double2*>(eta) + (static_cast<size_t>(r) * 4 + m) * l.E;
+        j.E = l.E;
+        j.nord = l.nord;
       }
-    pm_status e = st(timed(PM_PHASE_INVERSE, s, [&] { return launch_inv_combine(ca, L, E, fout, s); }));
+    pm_status e = st(timed(PM_PHASE_OTHER, s, [&] { return launch_refresh(ra, s); }));
     if (e) return e;
   }
-  return PM_OK;
+  const double dt = p->eps;
+  Run run(U, R, p, prec, workspace, s);
+  // leapfrog: half kick, (drift, kick) x (nsteps - 1), drift, half kick;
+  // every kick but the last also forms the exponent of the next drift
+  pm_status e = run.links_forward();
+  if (!e) e = run.staples();
+  if (!e) e = run.force(nullptr, Pg, 0.5 * dt, dt, true);
+  for (int i = 0; i < nsteps && !e; ++i) {
+    const bool last = i == nsteps - 1;
+    e = run.exp_and_update();
+    if (!e) e = run.links_forward();
+    if (!e) e = run.staples();
+    if (!e) e = run.force(nullptr, Pg, last ? 0.5 * dt : dt, dt, !last);
+  }
+  return e;
 }
 
 }  // namespace pm

@@ -54,19 +54,53 @@ struct TraceArgs { TraceJob jobs[kMaxTransformJobs]; int njobs; };
 struct ForceJob {
   const double2* M;        // [nord][n][n], unscaled
   const double2* tr;       // [nord] traces of M
-  const double2* eta;      // [n][n] noise
-  double2* Y;              // [nord][n][n] output, multiplied by s^k
+  const double2* eta;      // [n][n] noise (Langevin form)
+  double2* P;              // [nord][n][n] momentum series, updated (MD form)
+  double2* Y;              // [nord][n][n] output, multiplied by s^k, or null (MD form only)
   const ScaleRec* rec;
   int n;
   int nord;
 };
 constexpr int kMaxForceJobs = 48;
-struct ForceArgs { ForceJob jobs[kMaxForceJobs]; double eps; double noise_amp; int njobs; };
+// md == 0: Y = i (eps F + sqrt(2 eps) eta g).  md == 1: P^(k) += kick F^(k)
+// for k >= 1, then Y = i dt P.
+struct ForceArgs {
+  ForceJob jobs[kMaxForceJobs];
+  double eps;
+  double noise_amp;
+  double kick;
+  double dt;
+  int md;
+  int njobs;
+};
+
+// Momentum refresh: P^(1) = eta, every other order zero.
+struct RefreshJob {
+  double2* P;              // [nord][E]
+  const double2* eta;      // [E]
+  int E;
+  int nord;
+};
+constexpr int kMaxRefreshJobs = 64;
+struct RefreshArgs { RefreshJob jobs[kMaxRefreshJobs]; int njobs; };
+constexpr int kMaxMdSteps = 100000;
+
+// x^(k) <- s^k x^(k) in place (order k of a [nord][E] series).
+struct SeriesScaleJob {
+  double2* x;
+  const ScaleRec* rec;
+  int E;
+  int nord;
+};
+constexpr int kMaxSeriesScaleJobs = 64;
+struct SeriesScaleArgs { SeriesScaleJob jobs[kMaxSeriesScaleJobs]; int njobs; };
 
 hipError_t launch_retrunc(const RetruncArgs& a, int L, int max_entries, FourierType fin, FourierType fout,
                           hipStream_t s);
 hipError_t launch_inv_combine(const CombineArgs& a, int L, int max_entries, FourierType fin, hipStream_t s);
 hipError_t launch_trace(const TraceArgs& a, int max_nord, hipStream_t s);
 hipError_t launch_force(const ForceArgs& a, int n, int max_nord, hipStream_t s);
+hipError_t launch_refresh(const RefreshArgs& a, hipStream_t s);
+hipError_t launch_series_scale(const SeriesScaleArgs& a, int max_nord, hipStream_t s);
 
 }  // namespace pm

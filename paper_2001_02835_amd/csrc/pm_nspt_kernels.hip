@@ -10,9 +10,13 @@
 //  * k_inv_combine  - inverse transform of a weighted sum of products
 //                     (the staple combination), with 1/L and unscaling.
 //  * k_trace        - Tr M^(k) for every order.
-//  * k_force        - D = M - M^+, F = i (D - Tr D / N), and the
-//                     drift-plus-noise exponent Y = i X = i (eps F + sqrt(2 eps) eta g),
-//                     rescaled by s^k for the following products.
+//  * k_force        - D = M - M^+, F = i (D - Tr D / N), and either the
+//                     drift-plus-noise exponent Y = i X = i (eps F + sqrt(2 eps) eta g)
+//                     (Langevin) or the momentum kick P += c F with the
+//                     exponent Y = i dt P (molecular dynamics), rescaled by
+//                     s^k for the following products.
+//  * k_refresh      - momentum refresh, P^(1) = eta and all other orders zero.
+//  * k_series_scale - x^(k) <- s^k x^(k) in place.
 //
 // All series here are FP64 complex [nord][n][n]; Fourier coefficients use the
 // formats of the product kernels (FP64, FP32 or split BF16).
@@ -112,6 +116,31 @@ __global__ __launch_bounds__(kFftThreads, fft_min_waves<L>()) void k_inv_combine
       if (k >= jb.kmin) jb.dst[static_cast<size_t>(k) * E + e] = cscale(acc[k][el], jb.rec->sinv[k]);
 }
 
+// ---------------------------------------------------------------- refresh
+
+// P^(1) = eta, every other order zero (grid-stride over the series).
+__global__ __launch_bounds__(256) void k_refresh(RefreshArgs args) {
+  const RefreshJob& jb = args.jobs[blockIdx.y];
+  const size_t total = static_cast<size_t>(jb.nord) * jb.E;
+  for (size_t t = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; t < total;
+       t += static_cast<size_t>(gridDim.x) * 256) {
+    const size_t k = t / jb.E;
+    jb.P[t] = (k == 1) ? jb.eta[t - jb.E] : make_double2(0.0, 0.0);
+  }
+}
+
+// ------------------------------------------------------------ series scale
+
+// x^(k) <- s^k x^(k); grid (entry blocks, order, job).
+__global__ __launch_bounds__(256) void k_series_scale(SeriesScaleArgs args) {
+  const SeriesScaleJob& jb = args.jobs[blockIdx.z];
+  const int k = blockIdx.y;
+  if (k >= jb.nord) return;
+  const double f = jb.rec->spow[k];
+  double2* x = jb.x + static_cast<size_t>(k) * jb.E;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < jb.E; e += gridDim.x * 256) x[e] = cscale(x[e], f);
+}
+
 // ------------------------------------------------------------------ trace
 
 __global__ __launch_bounds__(64) void k_trace(TraceArgs args) {
@@ -147,7 +176,7 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs args) {
   const int I0 = ti * kTile, J0 = tj * kTile;
   const size_t E = static_cast<size_t>(n) * n;
   const double2* Mk = jb.M + static_cast<size_t>(k) * E;
-  double2* Yk = jb.Y + static_cast<size_t>(k) * E;
+  double2* Yk = jb.Y ? jb.Y + static_cast<size_t>(k) * E : nullptr;
   const int tx = threadIdx.x & (kTile - 1), ty = threadIdx.x / kTile;   // 32 x 8
   // stage M[J0 + a][I0 + b] at mir[a][b]
   for (int a = ty; a < kTile; a += 8) {
@@ -169,14 +198,23 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs args) {
       // D = M - M^+; Tr D = 2 i Im Tr M
       double2 d = make_double2(mij.x - mji.x, mij.y + mji.y);
       if (i == j) d.y -= 2.0 * tr.y / n;
-      y = make_double2(-eps * d.x, -eps * d.y);       // i X = -eps (D - Tr D / N)
-      if (k == 1) {
-        const double2 et = jb.eta[static_cast<size_t>(i) * n + j];
-        y = make_double2(y.x - noise * et.y, y.y + noise * et.x);   // + i sqrt(2 eps) eta
+      if (args.md) {
+        // F = i (D - Tr D / N); P += kick F; Y = i dt P
+        const size_t at = static_cast<size_t>(k) * E + static_cast<size_t>(i) * n + j;
+        double2 pv = jb.P[at];
+        pv = make_double2(pv.x - args.kick * d.y, pv.y + args.kick * d.x);
+        jb.P[at] = pv;
+        y = make_double2(-args.dt * pv.y, args.dt * pv.x);
+      } else {
+        y = make_double2(-eps * d.x, -eps * d.y);     // i X = -eps (D - Tr D / N)
+        if (k == 1) {
+          const double2 et = jb.eta[static_cast<size_t>(i) * n + j];
+          y = make_double2(y.x - noise * et.y, y.y + noise * et.x);   // + i sqrt(2 eps) eta
+        }
       }
       y = cscale(y, scale);
     }
-    Yk[static_cast<size_t>(i) * n + j] = y;
+    if (Yk) Yk[static_cast<size_t>(i) * n + j] = y;
   }
 }
 
@@ -232,6 +270,18 @@ hipError_t launch_inv_combine(const CombineArgs& a, int L, int max_entries, Four
   if (ns == kMaxCombine)
     return fin == kF64 ? combine_dispatch<kF64, kMaxCombine>(a, L, g, s) : combine_dispatch<kF32, kMaxCombine>(a, L, g, s);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_refresh(const RefreshArgs& a, hipStream_t s) {
+  if (a.njobs <= 0) return hipSuccess;
+  k_refresh<<<dim3(256, a.njobs), 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_series_scale(const SeriesScaleArgs& a, int max_nord, hipStream_t s) {
+  if (a.njobs <= 0) return hipSuccess;
+  k_series_scale<<<dim3(64, max_nord, a.njobs), 256, 0, s>>>(a);
+  return hipGetLastError();
 }
 
 hipError_t launch_trace(const TraceArgs& a, int max_nord, hipStream_t s) {

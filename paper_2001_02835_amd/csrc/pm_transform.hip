@@ -107,10 +107,12 @@ __global__ __launch_bounds__(256) void k_norms(NormArgs args) {
 // c_m = sum_j a_j b_{m-j} (m <= 2 ntrunc, the orders of the full product,
 // including those the truncation discards), minimise the spread
 //   f(t) = max_m (log c_m + m t) - min_{k <= ntrunc} (log c_k + k t)
-// over the nonzero c.  f is convex and piecewise linear.  One wavefront
+// over the nonzero c (per-order norms below 1e-15 of the operand's largest
+// are treated as zero).  f is convex and piecewise linear.  One wavefront
 // evaluates it on a 64-point grid; three refinement rounds shrink the grid
 // spacing by 32 each.
 constexpr double kAbsent = 1e300;
+constexpr double kNoiseFloor = 1e-15;
 
 __device__ __forceinline__ double lane_value(double v, int src) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
@@ -142,6 +144,16 @@ __global__ __launch_bounds__(64) void k_scale(ScaleArgs args) {
       na = sqrt((sa[0] + sa[1]) + (sa[2] + sa[3]));
       nb = sqrt((sb[0] + sb[1]) + (sb[2] + sb[3]));
     }
+    // orders below 1e-15 of an operand's largest one carry no information in
+    // FP64 (e.g. the rounding residue of a product at orders that vanish
+    // exactly); they are left out so that s is not chosen to lift them
+    double ma = na, mb = nb;
+    for (int off = 32; off > 0; off >>= 1) {
+      ma = fmax(ma, __shfl_xor(ma, off));
+      mb = fmax(mb, __shfl_xor(mb, off));
+    }
+    if (na < kNoiseFloor * ma) na = 0.0;
+    if (nb < kNoiseFloor * mb) nb = 0.0;
     // c_m = sum_j a_j b_{m-j}: lane m holds c_m (m < 64) and c_{m+64}
     double c0 = 0.0, c1 = 0.0;
     const int nm = 2 * nord - 1;

@@ -514,4 +514,11 @@ pm_status nspt_langevin_step(void* U, const void* eta, int replicas, const nspt_
                        static_cast<hipStream_t>(stream));
 }
 
+pm_status nspt_md_trajectory(void* U, void* P, const void* eta, int replicas, const nspt_params* params,
+                             int nsteps, int precision, void* workspace, size_t workspace_bytes,
+                             void* stream) {
+  return pm::nspt_md(U, P, eta, replicas, params, nsteps, precision, workspace, workspace_bytes,
+                     static_cast<hipStream_t>(stream));
+}
+
 }  // extern "C"

@@ -135,3 +135,20 @@ def test_nspt_rejects_bad_arguments():
     assert lib.nspt_langevin_step(FAKE_A, FAKE_B, 2, ctypes.byref(good), 0, FAKE_WS, need - 1, None) == \
         nat.PM_ERR_WORKSPACE
     assert lib.nspt_langevin_step(None, FAKE_B, 2, ctypes.byref(good), 0, FAKE_WS, need, None) == nat.PM_ERR_INVALID
+
+
+def test_md_trajectory_rejects_bad_arguments():
+    lib = pm.lib()
+    good = nat.NsptParams(9, 3, 1, 7, 0.1)
+    need = lib.nspt_workspace_size(1, ctypes.byref(good), 0)
+    P = FAKE_A + (1 << 32)
+    eta = FAKE_B + (1 << 33)
+    call = lambda U, Pp, e, R, prm, ns, ws, nb: lib.nspt_md_trajectory(U, Pp, e, R, ctypes.byref(prm), ns, 0, ws,
+                                                                       nb, None)
+    assert call(FAKE_A, P, eta, 1, good, 0, FAKE_WS, need) == nat.PM_ERR_INVALID          # nsteps < 1
+    assert call(FAKE_A, P, eta, 1, good, 100001, FAKE_WS, need) == nat.PM_ERR_INVALID     # nsteps too large
+    assert call(None, P, eta, 1, good, 4, FAKE_WS, need) == nat.PM_ERR_INVALID            # no U
+    assert call(FAKE_A, None, eta, 1, good, 4, FAKE_WS, need) == nat.PM_ERR_INVALID       # no P
+    assert call(FAKE_A, FAKE_A, eta, 1, good, 4, FAKE_WS, need) == nat.PM_ERR_INVALID     # U and P overlap
+    assert call(FAKE_A, P, eta, 1, good, 4, FAKE_WS, need - 1) == nat.PM_ERR_WORKSPACE
+    assert call(FAKE_A, P, eta, 1, nat.NsptParams(9, 3, 1, 7, 0.0), 4, FAKE_WS, need) == nat.PM_ERR_INVALID
