@@ -187,6 +187,37 @@ def bench_md(torch, synth, pm, dev, nsteps):
     return res
 
 
+def bench_crossover(torch, synth, pm, dev, reps=20):
+    """Naive-CONV (direct eq. (5)) against FFT-CONV for one FP64 product at
+    N=225 and growing ntrunc (entries N(0,1)*0.5^k): where the transform pays."""
+    n = 225
+    res = {"workload": "1 product N=225, FP64, entries N(0,1)*0.5^k; ms per product", "points": []}
+    for nt in (0, 1, 2, 3, 5, 7, 15, 31):
+        a = torch.from_numpy(synth.random_series(synth.rng_for(7, nt, 0), n, nt, 0.5)).to(dev)
+        b = torch.from_numpy(synth.random_series(synth.rng_for(7, nt, 1), n, nt, 0.5)).to(dev)
+        c = torch.empty_like(a)
+        items = [dict(A=a, B=b, C=c)]
+        ws = pm.workspace(pm.batched_workspace_size(items, "fp64"), dev)
+        t = {}
+        for name, fn in (("naive", lambda: pm.polymat_mul_naive(a, b, C=c)),
+                         ("fftconv", lambda: pm.polymat_mul_batched(items, "fp64", ws=ws))):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            t[name] = e0.elapsed_time(e1) / reps
+        res["points"].append({"ntrunc": nt, "naive_ms": round(t["naive"], 4), "fftconv_ms": round(t["fftconv"], 4),
+                              "naive_products": (nt + 1) * (nt + 2) // 2, "fft_modes": pm.transform_length(nt)})
+        del ws
+    return res
+
+
 def cpu_baseline(seconds: float):
     """The FP64 oracle (naive star product, BLAS matmul per term) on the host
     cores, on products of the headline shape until `seconds` have elapsed."""
@@ -309,6 +340,7 @@ def main(argv=None):
         out["batched_uneven"] = bench_uneven(torch, synth, pm, dev, max(args.steps // 20, 3))
         out["nspt_step"] = bench_nspt(torch, synth, pm, dev, args.nspt_steps)
         out["nspt_md"] = bench_md(torch, synth, pm, dev, args.md_steps)
+        out["naive_vs_fftconv"] = bench_crossover(torch, synth, pm, dev)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

@@ -97,10 +97,29 @@ int polymat_transform_length(int ntrunc);
  *   precision  PM_PREC_* above.     scale: see "Rescaling" above.
  *   workspace  >= polymat_workspace_size(n, ntrunc, precision, 1) bytes.
  * Returns PM_OK or an error status (nothing enqueued on error).
+ * With PM_PREC_FP64, ntrunc == 0 and C not aliasing A or B the call takes
+ * the direct form of polymat_mul_naive instead (one matrix product against
+ * L = 4 mode products plus the transforms; from ntrunc = 1 on the transform
+ * path is faster for one product at N = 225); the arguments are validated
+ * the same way.
  */
 pm_status polymat_mul(const void* A, const void* B, void* C, int n, int ntrunc,
                       int precision, double scale, void* workspace,
                       size_t workspace_bytes, void* stream);
+
+/*
+ * polymat_mul_naive - the same product by the direct convolution of eq. (5)
+ * (the paper's Naive-CONV, Section 2), in FP64 on the matrix cores:
+ *     C^(k) = sum_{l=0..k} op_a(A)^(l) op_b(B)^(k-l),   k = 0..ntrunc,
+ * one N x N x (k+1)N complex product per order k, no transform and no
+ * rescaling; cost (ntrunc+1)(ntrunc+2)/2 matrix products.
+ *   A, B, C    device complex128 [ntrunc+1][n][n]; C must not overlap A or B
+ *              (PM_ERR_INVALID).  op_a, op_b: PM_OP_N or PM_OP_C.
+ *   n          1 <= n <= PM_MAX_N.   ntrunc: 0 <= ntrunc <= PM_MAX_NTRUNC.
+ * No workspace.  Returns PM_OK or an error status (nothing enqueued on error).
+ */
+pm_status polymat_mul_naive(const void* A, const void* B, void* C, int n, int ntrunc,
+                            int op_a, int op_b, void* stream);
 
 /* Workspace bytes for `count` products of one shape (count >= 1), or 0 if
  * the arguments are invalid. */

@@ -99,6 +99,24 @@ def batched_workspace_size(items: Sequence[dict], precision="fp64") -> int:
     return int(nat.lib().polymat_batched_workspace_size(arr, len(items), _prec(precision)))
 
 
+def polymat_mul_naive(A: torch.Tensor, B: torch.Tensor, C: Optional[torch.Tensor] = None,
+                      op_a: int = 0, op_b: int = 0) -> torch.Tensor:
+    """C = op_a(A) * op_b(B) by the direct convolution of eq. (5) (FP64); C must
+    not overlap A or B.  Series [ntrunc+1, n, n] complex128."""
+    _series_check(A, "A")
+    _series_check(B, "B")
+    if A.shape != B.shape or A.dim() != 3 or A.shape[1] != A.shape[2]:
+        raise ValueError("A and B must be [ntrunc+1, n, n] of one shape")
+    if C is None:
+        C = torch.empty_like(A)
+    _series_check(C, "C")
+    nt1, n = A.shape[0], A.shape[1]
+    st = nat.lib().polymat_mul_naive(A.data_ptr(), B.data_ptr(), C.data_ptr(), n, nt1 - 1, int(op_a), int(op_b),
+                                     _stream_ptr(A.device))
+    nat.check(st, "polymat_mul_naive")
+    return C
+
+
 def polymat_mul_batched(items: Sequence[dict], precision="fp64", ws: Optional[torch.Tensor] = None):
     """Each item: dict(A=, B=, C=, op_a=0|1, op_b=0|1, scale=0.0); C = op_a(A) * op_b(B)."""
     if not items:

@@ -14,6 +14,7 @@ namespace pm {
 
 hipError_t launch_gemm_f64(const GemmArgs& a, int cfg, bool g3, hipStream_t s);
 hipError_t launch_gemm_f32(const GemmArgs& a, int cfg, bool g3, hipStream_t s);
+hipError_t launch_gemm_conv_f64(const GemmArgs& a, bool g3, hipStream_t s);
 
 namespace {
 
@@ -57,6 +58,11 @@ int gemm_config(FourierType t, int n) {
   for (int i = 0; i < nrows; ++i)
     if (n <= rows[i].n_max) return rows[i].cfg;
   return rows[nrows - 1].cfg;
+}
+
+hipError_t launch_conv(const GemmArgs& a, hipStream_t s) {
+  if (a.njobs <= 0 || a.total_tiles <= 0) return hipSuccess;
+  return launch_gemm_conv_f64(a, g_gemm_g3, s);
 }
 
 hipError_t launch_gemm(const GemmArgs& a, FourierType t, int cfg, hipStream_t s) {

@@ -16,4 +16,8 @@ hipError_t launch_gemm_f64(const GemmArgs& a, int cfg, bool g3, hipStream_t s) {
   }
 }
 
+hipError_t launch_gemm_conv_f64(const GemmArgs& a, bool g3, hipStream_t s) {
+  return launch_cgemm_conv<double>(a, g3, s);
+}
+
 }  // namespace pm

@@ -293,7 +293,12 @@ struct Tile2 {
   static constexpr size_t kLdsBytes = sizeof(T2) * (kAElems + kBElems);
 };
 
-template <typename T, int WM, int WN, int WGM, int WGN, bool OPA, bool OPB, bool G3>
+// CONV selects the direct form of eq. (5) instead of a Fourier mode: p is an
+// output order k, A and B are time-domain series [L = ntrunc+1][n][n], and
+// the contraction runs over (l, kk) for l = 0..k: C^(k) = sum_l opA(A)^(l)
+// opB(B)^(k-l), one K block of n per term (each block zero-padded to whole
+// chunks).
+template <typename T, int WM, int WN, int WGM, int WGN, bool OPA, bool OPB, bool G3, bool CONV = false>
 __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, int tn, char* smem) {
   using C = Cx<T>;
   using T2 = typename C::T2;
@@ -307,11 +312,12 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
 
   const int n = jb.n, L = jb.L;
   const size_t E = static_cast<size_t>(n) * n;
-  const int pa = OPA ? (L - p) % L : p;
-  const int pb = OPB ? (L - p) % L : p;
+  const int pa = CONV ? 0 : (OPA ? (L - p) % L : p);
+  const int pb = CONV ? 0 : (OPB ? (L - p) % L : p);
   const T2* __restrict__ Ag = reinterpret_cast<const T2*>(jb.A) + pa * E;
   const T2* __restrict__ Bg = reinterpret_cast<const T2*>(jb.B) + pb * E;
   T2* __restrict__ Cg = reinterpret_cast<T2*>(jb.C) + static_cast<size_t>(p) * E;
+  const int cpl = (n + BK - 1) / BK;   // chunks per term (CONV)
   const int row0 = tm * BM, col0 = tn * BN;
 
   const int tid = threadIdx.x;
@@ -336,13 +342,24 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
 
   T2 ra[G::LA], rb[G::LB];
   bool oka[G::LA], okb[G::LB];
-  auto load_chunk = [&](int k0) {
+  // chunk c: its k offset within the current term, and (CONV) the term's
+  // operand orders l and p - l
+  auto chunk_k0 = [&](int c) { return CONV ? (c - (c / cpl) * cpl) * BK : c * BK; };
+  auto load_chunk = [&](int c) {
+    const int k0 = chunk_k0(c);
+    const T2* __restrict__ Ac = Ag;
+    const T2* __restrict__ Bc = Bg;
+    if constexpr (CONV) {
+      const int l = c / cpl;
+      Ac = Ag + static_cast<size_t>(l) * E;
+      Bc = Bg + static_cast<size_t>(p - l) * E;
+    }
 #pragma unroll
     for (int u = 0; u < G::LA; ++u) {
       const int gi = row0 + a_i[u], gk = k0 + a_k[u];
       const bool ok = gi < n && gk < n;
       const int off = ok ? (OPA ? gk * n + gi : gi * n + gk) : 0;
-      ra[u] = Ag[off];
+      ra[u] = Ac[off];
       oka[u] = ok;
     }
 #pragma unroll
@@ -350,7 +367,7 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
       const int gj = col0 + b_j[u], gk = k0 + b_k[u];
       const bool ok = gj < n && gk < n;
       const int off = ok ? (OPB ? gj * n + gk : gk * n + gj) : 0;
-      rb[u] = Bg[off];
+      rb[u] = Bc[off];
       okb[u] = ok;
     }
   };
@@ -475,14 +492,14 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
     }
   };
 
-  const int nchunks = (n + BK - 1) / BK;
+  const int nchunks = CONV ? (p + 1) * cpl : cpl;
   load_chunk(0);
   store_chunk(0);
   __syncthreads();
   for (int c = 0; c < nchunks; ++c) {
     const int buf = c & 1;
-    const int k0 = c * BK;
-    if (c + 1 < nchunks) load_chunk(k0 + BK);
+    const int k0 = chunk_k0(c);
+    if (c + 1 < nchunks) load_chunk(c + 1);
     // k-step s of the chunk contracts k = k0 + 4 g + s; it is needed when k0 + s < n
     T2 fa0[WM], fb0[WN], fa1[WM], fb1[WN];
     read_frags(buf, 0, fa0, fb0);
@@ -562,13 +579,14 @@ __device__ __forceinline__ void gemm_task(const GemmJob* jobs, int njobs, int id
   tn = rem - tm * jb.tiles_n;
 }
 
-template <typename T, int WM, int WN, int WGM, int WGN, bool OPA, bool OPB, bool G3>
+template <typename T, int WM, int WN, int WGM, int WGN, bool OPA, bool OPB, bool G3, bool CONV = false>
 __global__ __launch_bounds__(kWave * WGM * WGN) void k_cgemm2(GemmArgs args) {
   __shared__ __attribute__((aligned(16))) char smem[Tile2<T, WM, WN, WGM, WGN>::kLdsBytes];
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   int jidx, p, tm, tn;
   gemm_task(args.jobs, args.njobs, id, jidx, p, tm, tn);
-  cgemm2_tile<T, WM, WN, WGM, WGN, OPA, OPB, G3>(args.jobs[jidx], p, tm, tn, smem);
+  if constexpr (CONV) p = args.jobs[jidx].L - 1 - p;   // highest orders (most terms) first
+  cgemm2_tile<T, WM, WN, WGM, WGN, OPA, OPB, G3, CONV>(args.jobs[jidx], p, tm, tn, smem);
 }
 
 }  // namespace gemm_detail
@@ -597,6 +615,29 @@ hipError_t launch_cgemm_cfg(const GemmArgs& a, bool g3, hipStream_t s) {
     else PM_K(true, true, false);
   }
 #undef PM_K
+  return hipGetLastError();
+}
+
+// Direct (naive) convolution form: jobs hold time-domain series and L is the
+// number of orders; one 64 x 64 tile shape (the FP64 default).
+template <typename T>
+hipError_t launch_cgemm_conv(const GemmArgs& a, bool g3, hipStream_t s) {
+  using namespace gemm_detail;
+  const int oa = a.jobs[0].opA, ob = a.jobs[0].opB;   // shared by all jobs of a launch
+  const int g = a.total_tiles;
+#define PM_KC(OA, OB, G3) k_cgemm2<T, 2, 1, 2, 4, OA, OB, G3, true><<<g, kWave * 8, 0, s>>>(a)
+  if (g3) {
+    if (!oa && !ob) PM_KC(false, false, true);
+    else if (!oa && ob) PM_KC(false, true, true);
+    else if (oa && !ob) PM_KC(true, false, true);
+    else PM_KC(true, true, true);
+  } else {
+    if (!oa && !ob) PM_KC(false, false, false);
+    else if (!oa && ob) PM_KC(false, true, false);
+    else if (oa && !ob) PM_KC(true, false, false);
+    else PM_KC(true, true, false);
+  }
+#undef PM_KC
   return hipGetLastError();
 }
 

@@ -98,6 +98,10 @@ GemmShape gemm_shape(FourierType t, int cfg);
 int gemm_config(FourierType t, int n);          // tuned choice for matrix size n
 bool gemm_uses_g3();                            // three-product complex form in use
 hipError_t launch_gemm(const GemmArgs& a, FourierType t, int cfg, hipStream_t s);
+// Direct convolution (eq. (5)) of FP64 time-domain series: job.L = ntrunc + 1
+// output orders, 64 x 64 tiles (tiles_m = tiles_n = ceil(n / 64)).
+constexpr int kConvTile = 64;
+hipError_t launch_conv(const GemmArgs& a, hipStream_t s);
 int gemm_tile_bf16();
 hipError_t launch_gemm_bf16(const GemmArgs& a, hipStream_t s);
 

@@ -152,3 +152,15 @@ def test_md_trajectory_rejects_bad_arguments():
     assert call(FAKE_A, FAKE_A, eta, 1, good, 4, FAKE_WS, need) == nat.PM_ERR_INVALID     # U and P overlap
     assert call(FAKE_A, P, eta, 1, good, 4, FAKE_WS, need - 1) == nat.PM_ERR_WORKSPACE
     assert call(FAKE_A, P, eta, 1, nat.NsptParams(9, 3, 1, 7, 0.0), 4, FAKE_WS, need) == nat.PM_ERR_INVALID
+
+
+def test_naive_rejects_bad_arguments():
+    lib = pm.lib()
+    f = lib.polymat_mul_naive
+    assert f(None, FAKE_B, FAKE_C, 9, 3, 0, 0, None) == nat.PM_ERR_INVALID
+    assert f(FAKE_A, FAKE_B, FAKE_C, 0, 3, 0, 0, None) == nat.PM_ERR_INVALID          # n < 1
+    assert f(FAKE_A, FAKE_B, FAKE_C, 9, -1, 0, 0, None) == nat.PM_ERR_INVALID         # ntrunc < 0
+    assert f(FAKE_A, FAKE_B, FAKE_C, 9, 64, 0, 0, None) == nat.PM_ERR_UNSUPPORTED     # ntrunc too large
+    assert f(FAKE_A, FAKE_B, FAKE_C, 9, 3, 2, 0, None) == nat.PM_ERR_INVALID          # bad op
+    assert f(FAKE_A, FAKE_B, FAKE_A, 9, 3, 0, 0, None) == nat.PM_ERR_INVALID          # C aliases A
+    assert f(FAKE_A + 8, FAKE_B, FAKE_C, 9, 3, 0, 0, None) == nat.PM_ERR_INVALID      # misaligned

@@ -173,3 +173,43 @@ def _cached_star(a, b, key):
     if key not in _STAR_CACHE:
         _STAR_CACHE[key] = ser.star(a, b)
     return _STAR_CACHE[key]
+
+
+@pytest.mark.parametrize("n", [1, 17, 33, 65, 100])
+@pytest.mark.parametrize("nt", [0, 1, 2, 5, 15])
+def test_naive_direct_form_matches_oracle(n, nt):
+    a, b = rs(100 + n, n, nt, 0.9), rs(200 + n, n, nt, 0.9)
+    for op_a in (0, 1):
+        for op_b in (0, 1):
+            c = to_host(pm.polymat_mul_naive(to_dev(a), to_dev(b), op_a=op_a, op_b=op_b))
+            ref = ser.star(ser.dagger(a) if op_a else a, ser.dagger(b) if op_b else b)
+            e = order_errors(c, ref)
+            assert e.max() < 1e-12, (op_a, op_b, e)
+
+
+def test_naive_direct_form_paper_scale():
+    n, nt = 225, 7
+    a = synth.random_series(synth.rng_for(4, 0, 0), n, nt, 0.5)
+    b = synth.random_series(synth.rng_for(4, 0, 1), n, nt, 0.5)
+    c = to_host(pm.polymat_mul_naive(to_dev(a), to_dev(b)))
+    assert order_errors(c, ser.star(a, b)).max() < 1e-12
+
+
+def test_naive_rejects_aliasing_output():
+    a = to_dev(rs(300, 9, 2))
+    b = to_dev(rs(301, 9, 2))
+    with pytest.raises(pm.PolymatError):
+        pm.polymat_mul_naive(a, b, C=a)
+
+
+@pytest.mark.parametrize("nt", [0, 1, 2])
+def test_short_series_dispatch_and_alias_fallback(nt):
+    # polymat_mul takes the direct form for short FP64 series, and the
+    # transform path when C aliases an operand; both agree with the oracle
+    a, b = rs(310 + nt, 40, nt), rs(320 + nt, 40, nt)
+    ref = ser.star(a, b)
+    c = to_host(pm.polymat_mul(to_dev(a), to_dev(b)))
+    assert order_errors(c, ref).max() < 1e-12
+    da, db = to_dev(a), to_dev(b)
+    pm.polymat_mul(da, db, C=da)
+    assert order_errors(to_host(da), ref).max() < TOL["fp64"]
