@@ -278,6 +278,22 @@ pm_status nspt_md_trajectory(void* U, void* P, const void* eta, int replicas,
                              void* workspace, size_t workspace_bytes,
                              void* stream);
 
+/*
+ * nspt_action - the action of eq. (1) at beta = 1 as a series in g, for
+ * `replicas` link sets (the observable of the plaquette, i.e. the 1x1
+ * Wilson loop: W^(k) = delta_k0 - S^(k) / (12 N)):
+ *   S^(k) = sum_{mu != nu} Tr[ delta_k0 1 - z_{mu nu} (U_mu * U_nu * U_mu^+ * U_nu^+)^(k) ]
+ *         = 12 N delta_k0 - 2 Re sum_{mu < nu} z_{mu nu} Tr (U_mu * U_nu * U_mu^+ * U_nu^+)^(k).
+ *   U    device complex128 [replicas][4][ntrunc+1][n][n] (read only).
+ *   S    device float64 [replicas][ntrunc+1], written.
+ * precision applies to the products.  The workspace is the one of
+ * nspt_langevin_step (nspt_workspace_size); U, S and the workspace must not
+ * overlap (PM_ERR_INVALID).
+ */
+pm_status nspt_action(const void* U, int replicas, const nspt_params* params,
+                      int precision, double* S, void* workspace,
+                      size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

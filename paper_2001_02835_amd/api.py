@@ -207,6 +207,24 @@ def nspt_md_trajectory(U: torch.Tensor, P: torch.Tensor, params: nat.NsptParams,
     return U, P
 
 
+def nspt_action(U: torch.Tensor, params: nat.NsptParams, precision="fp64",
+                ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Action series S^(k) (float64 [R, ntrunc+1]) of link series U [R, 4, ntrunc+1, n, n]."""
+    _series_check(U, "U")
+    R, nord = U.shape[0], U.shape[2]
+    p = _prec(precision)
+    need = nat.lib().nspt_workspace_size(R, ctypes.byref(params), p)
+    if need == 0:
+        raise ValueError("invalid NSPT parameters")
+    if ws is None:
+        ws = workspace(need, U.device)
+    S = torch.empty((R, nord), dtype=torch.float64, device=U.device)
+    st = nat.lib().nspt_action(U.data_ptr(), R, ctypes.byref(params), p, S.data_ptr(), ws.data_ptr(), ws.numel(),
+                               _stream_ptr(U.device))
+    nat.check(st, "nspt_action")
+    return S
+
+
 def timing_enable(on: bool = True) -> None:
     """Bracket every library launch with HIP events (for measurement only)."""
     nat.check(nat.lib().polymat_timing_enable(1 if on else 0), "polymat_timing_enable")

@@ -11,6 +11,8 @@ namespace pm {
 size_t nspt_workspace_bytes(int replicas, const nspt_params* params, int precision);
 pm_status nspt_step(void* U, const void* eta, int replicas, const nspt_params* params, int precision,
                     void* workspace, size_t workspace_bytes, hipStream_t stream);
+pm_status nspt_series_action(const void* U, int replicas, const nspt_params* params, int precision, double* S,
+                             void* workspace, size_t workspace_bytes, hipStream_t stream);
 pm_status nspt_md(void* U, void* P, const void* eta, int replicas, const nspt_params* params, int nsteps,
                   int precision, void* workspace, size_t workspace_bytes, hipStream_t stream);
 

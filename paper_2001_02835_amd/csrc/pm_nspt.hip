@@ -394,6 +394,84 @@ struct Run {
     return st(timed(PM_PHASE_OTHER, s, [&] { return launch_trace(ta, nord, s); }));
   }
 
+  // ---- action series S^(k) = 12 N delta_k0 - 2 Re sum_{m<n} z_mn Tr P_mn^(k)
+  //      (eq. (1) at beta = 1 expanded in g, the plaquettes
+  //      P_mn = U_m U_n U_m^+ U_n^+ = Q_mn * Q_nm^+) into S [R][nord]
+  pm_status action(double* S) {
+    const int n = l.n, E = l.E, nord = l.nord, L = l.L;
+    {
+      GemmBatch nn{fin, s, 0};
+      for (int r = 0; r < R; ++r)
+        for (int m = 0; m < 4; ++m)
+          for (int q = 0; q < 4; ++q)
+            if (m != q) nn.add(Ut(r, m), Ut(r, q), G(r, qslot[m][q]), n, L);
+      nn.flush();
+      if (nn.status) return PM_ERR_DEVICE;
+      RetruncBatch rt{&l, fout, fin, s};
+      rt.a.nadd = 0;
+      rt.a.idcoef = make_double2(0.0, 0.0);
+      for (int r = 0; r < R; ++r)
+        for (int slot = 0; slot < 12; ++slot) rt.add(G(r, slot), Xt(r, slot), nullptr, nullptr, 0);
+      rt.flush();
+      if (rt.status) return rt.status;
+      GemmBatch nc{fin, s, 1};
+      for (int r = 0; r < R; ++r)
+        for (int m = 0; m < 4; ++m)
+          for (int q = m + 1; q < 4; ++q) nc.add(Xt(r, qslot[m][q]), Xt(r, qslot[q][m]), G(r, pair[m][q]), n, L);
+      nc.flush();
+      if (nc.status) return PM_ERR_DEVICE;
+    }
+    // sum_{m<n} z_mn P_mn back to the time domain, one series per replica
+    {
+      CombineArgs ca{};
+      auto flush = [&]() -> pm_status {
+        if (ca.njobs == 0) return PM_OK;
+        pm_status e = st(timed(PM_PHASE_INVERSE, s, [&] { return launch_inv_combine(ca, L, E, fout, s); }));
+        ca.njobs = 0;
+        return e;
+      };
+      for (int r = 0; r < R; ++r) {
+        if (ca.njobs == kMaxCombineJobs) { pm_status e = flush(); if (e) return e; }
+        CombineJob& j = ca.jobs[ca.njobs++];
+        j.nsrc = 0;
+        for (int m = 0; m < 4; ++m)
+          for (int q = m + 1; q < 4; ++q) {
+            j.src[j.nsrc] = G(r, pair[m][q]);
+            j.coef[j.nsrc++] = twist(p, m, q);
+          }
+        j.dst = Mser(r, 0);
+        j.rec = rec;
+        j.E = E;
+        j.nord = nord;
+        j.kmin = 0;
+      }
+      pm_status e = flush();
+      if (e) return e;
+    }
+    TraceArgs ta{};
+    ActionArgs aa{};
+    aa.n = n;
+    aa.nord = nord;
+    for (int r = 0; r < R; ++r) {
+      if (ta.njobs == kMaxTransformJobs) {
+        pm_status e = st(timed(PM_PHASE_OTHER, s, [&] { return launch_trace(ta, nord, s); }));
+        if (e) return e;
+        ta.njobs = 0;
+      }
+      TraceJob& j = ta.jobs[ta.njobs++];
+      j.src = Mser(r, 0);
+      j.out = trc + static_cast<size_t>(r) * nord;
+      j.n = n;
+      j.nord = nord;
+    }
+    pm_status e = st(timed(PM_PHASE_OTHER, s, [&] { return launch_trace(ta, nord, s); }));
+    if (e) return e;
+    aa.tr = trc;
+    aa.S = S;
+    aa.count = R * nord;
+    return st(timed(PM_PHASE_OTHER, s, [&] { return launch_action(aa, s); }));
+  }
+
   // ---- force pass.  Langevin (P == nullptr): Y^1 = i X from the force and
   //      the noise.  MD: P^(k) += kick F^(k) (k >= 1) and, when write_y,
   //      Y^1 = i dt P (unscaled).
@@ -624,6 +702,24 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
   if (!e) e = run.staples();
   if (!e) e = run.force(static_cast<const double2*>(eta), nullptr, 0.0, 0.0, true);
   if (!e) e = run.exp_and_update();
+  return e;
+}
+
+pm_status nspt_series_action(const void* U, int R, const nspt_params* p, int prec, double* S, void* workspace,
+                             size_t workspace_bytes, hipStream_t s) {
+  if (!valid_params(R, p, prec)) return PM_ERR_INVALID;
+  if (!U || !S || !workspace) return PM_ERR_INVALID;
+  if (reinterpret_cast<uintptr_t>(U) % 16 || reinterpret_cast<uintptr_t>(S) % 8 ||
+      reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return PM_ERR_INVALID;
+  const Layout l = layout(R, p, prec);
+  if (workspace_bytes < l.total) return PM_ERR_WORKSPACE;
+  const size_t ub = static_cast<size_t>(R) * 4 * l.nord * l.E * 16, sb = static_cast<size_t>(R) * l.nord * 8;
+  if (overlaps(workspace, l.total, U, ub) || overlaps(workspace, l.total, S, sb) || overlaps(U, ub, S, sb))
+    return PM_ERR_INVALID;
+  Run run(const_cast<void*>(U), R, p, prec, workspace, s);   // U is only read
+  pm_status e = run.links_forward();
+  if (!e) e = run.action(S);
   return e;
 }
 

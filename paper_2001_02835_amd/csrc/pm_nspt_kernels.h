@@ -85,6 +85,9 @@ constexpr int kMaxRefreshJobs = 64;
 struct RefreshArgs { RefreshJob jobs[kMaxRefreshJobs]; int njobs; };
 constexpr int kMaxMdSteps = 100000;
 
+// S[i] = 12 n delta_{k0} - 2 Re tr[i], k = i mod nord (action series).
+struct ActionArgs { const double2* tr; double* S; int n; int nord; int count; };
+
 // x^(k) <- s^k x^(k) in place (order k of a [nord][E] series).
 struct SeriesScaleJob {
   double2* x;
@@ -101,6 +104,7 @@ hipError_t launch_inv_combine(const CombineArgs& a, int L, int max_entries, Four
 hipError_t launch_trace(const TraceArgs& a, int max_nord, hipStream_t s);
 hipError_t launch_force(const ForceArgs& a, int n, int max_nord, hipStream_t s);
 hipError_t launch_refresh(const RefreshArgs& a, hipStream_t s);
+hipError_t launch_action(const ActionArgs& a, hipStream_t s);
 hipError_t launch_series_scale(const SeriesScaleArgs& a, int max_nord, hipStream_t s);
 
 }  // namespace pm

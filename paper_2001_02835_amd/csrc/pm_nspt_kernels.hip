@@ -17,6 +17,7 @@
 //                     s^k for the following products.
 //  * k_refresh      - momentum refresh, P^(1) = eta and all other orders zero.
 //  * k_series_scale - x^(k) <- s^k x^(k) in place.
+//  * k_action       - action series from the traces of the plaquette sum.
 //
 // All series here are FP64 complex [nord][n][n]; Fourier coefficients use the
 // formats of the product kernels (FP64, FP32 or split BF16).
@@ -139,6 +140,15 @@ __global__ __launch_bounds__(256) void k_series_scale(SeriesScaleArgs args) {
   const double f = jb.rec->spow[k];
   double2* x = jb.x + static_cast<size_t>(k) * jb.E;
   for (int e = blockIdx.x * 256 + threadIdx.x; e < jb.E; e += gridDim.x * 256) x[e] = cscale(x[e], f);
+}
+
+// ----------------------------------------------------------------- action
+
+__global__ __launch_bounds__(256) void k_action(ActionArgs args) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= args.count) return;
+  const int k = i % args.nord;
+  args.S[i] = (k == 0 ? 12.0 * args.n : 0.0) - 2.0 * args.tr[i].x;
 }
 
 // ------------------------------------------------------------------ trace
@@ -281,6 +291,12 @@ hipError_t launch_refresh(const RefreshArgs& a, hipStream_t s) {
 hipError_t launch_series_scale(const SeriesScaleArgs& a, int max_nord, hipStream_t s) {
   if (a.njobs <= 0) return hipSuccess;
   k_series_scale<<<dim3(64, max_nord, a.njobs), 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_action(const ActionArgs& a, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  k_action<<<(a.count + 255) / 256, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -561,6 +561,12 @@ pm_status nspt_langevin_step(void* U, const void* eta, int replicas, const nspt_
                        static_cast<hipStream_t>(stream));
 }
 
+pm_status nspt_action(const void* U, int replicas, const nspt_params* params, int precision, double* S,
+                      void* workspace, size_t workspace_bytes, void* stream) {
+  return pm::nspt_series_action(U, replicas, params, precision, S, workspace, workspace_bytes,
+                                static_cast<hipStream_t>(stream));
+}
+
 pm_status nspt_md_trajectory(void* U, void* P, const void* eta, int replicas, const nspt_params* params,
                              int nsteps, int precision, void* workspace, size_t workspace_bytes,
                              void* stream) {

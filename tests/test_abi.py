@@ -164,3 +164,15 @@ def test_naive_rejects_bad_arguments():
     assert f(FAKE_A, FAKE_B, FAKE_C, 9, 3, 2, 0, None) == nat.PM_ERR_INVALID          # bad op
     assert f(FAKE_A, FAKE_B, FAKE_A, 9, 3, 0, 0, None) == nat.PM_ERR_INVALID          # C aliases A
     assert f(FAKE_A + 8, FAKE_B, FAKE_C, 9, 3, 0, 0, None) == nat.PM_ERR_INVALID      # misaligned
+
+
+def test_action_rejects_bad_arguments():
+    lib = pm.lib()
+    good = nat.NsptParams(9, 3, 1, 7, 0.01)
+    need = lib.nspt_workspace_size(1, ctypes.byref(good), 0)
+    S = FAKE_C
+    assert lib.nspt_action(None, 1, ctypes.byref(good), 0, S, FAKE_WS, need, None) == nat.PM_ERR_INVALID
+    assert lib.nspt_action(FAKE_A, 1, ctypes.byref(good), 0, None, FAKE_WS, need, None) == nat.PM_ERR_INVALID
+    assert lib.nspt_action(FAKE_A, 1, ctypes.byref(good), 0, S, FAKE_WS, need - 1, None) == nat.PM_ERR_WORKSPACE
+    assert lib.nspt_action(FAKE_A, 1, ctypes.byref(good), 0, FAKE_A, FAKE_WS, need, None) == nat.PM_ERR_INVALID
+    assert lib.nspt_action(FAKE_A, 0, ctypes.byref(good), 0, S, FAKE_WS, need, None) == nat.PM_ERR_INVALID

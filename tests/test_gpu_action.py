@@ -1,0 +1,60 @@
+"""GPU parity of the action series (nspt_action, the plaquette observable)
+against the oracle's series action, which is pinned to the dense action of
+eq. (1) by its Taylor expansion in g."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import nspt, series as ser, tek
+import paper_2001_02835_amd as pm
+from gpu_util import to_dev
+from nspt_util import series_links
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-11, "fp32": 1e-5, "bf16x3": 1e-4}
+
+
+def _scale(u):
+    """B_k = sum_{mu<nu} 2 sqrt(N) c_k, c the norm bound of the four-fold product
+    (|Tr X| <= sqrt(N) ||X||_F): the size of the terms that make up S^(k)."""
+    n = u.shape[-1]
+    nrm = np.sqrt(np.sum(np.abs(u) ** 2, axis=(-2, -1)))       # [4, nord]
+    nord = u.shape[1]
+    b = np.zeros(nord)
+    for m in range(4):
+        for q in range(m + 1, 4):
+            c = nrm[m]
+            for f in (nrm[q], nrm[m], nrm[q]):
+                c = np.convolve(c, f)[:nord]
+            b += 2 * np.sqrt(n) * c
+    b[0] += 12 * n
+    return b
+
+
+@pytest.mark.parametrize("L,k,nt,R", [(3, 1, 7, 2), (5, 2, 15, 1), (9, 2, 31, 1)])
+def test_action_matches_oracle(L, k, nt, R):
+    u = series_links(L, k, nt, 0.6, 40 + L, replicas=R)
+    z = tek.twist_tensor(L, k)
+    got = pm.nspt_action(to_dev(u), pm.nspt_params(L, k, nt, 0.01)).cpu().numpy()
+    for r in range(R):
+        ref = nspt.series_action(u[r], z)
+        err = np.abs(got[r] - ref) / _scale(u[r])
+        assert err.max() < TOL["fp64"], (r, err)
+
+
+def test_action_vanishes_at_the_vacuum():
+    L, k, nt = 5, 2, 7
+    u = synth.vacuum_links(L, k, nt, replicas=2)
+    got = pm.nspt_action(to_dev(u), pm.nspt_params(L, k, nt, 0.01)).cpu().numpy()
+    assert np.abs(got).max() < 1e-11 * 12 * L * L
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_action_precisions(prec):
+    L, k, nt = 5, 2, 15
+    u = series_links(L, k, nt, 0.6, 45)
+    got = pm.nspt_action(to_dev(u), pm.nspt_params(L, k, nt, 0.01), precision=prec).cpu().numpy()
+    ref = nspt.series_action(u[0], tek.twist_tensor(L, k))
+    err = np.abs(got[0] - ref) / _scale(u[0])
+    assert err.max() < TOL[prec], err
