@@ -134,3 +134,37 @@ def _refresh(eta_mu, nt):
     p = np.zeros((nt + 1,) + eta_mu.shape, dtype=np.complex128)
     p[1] = eta_mu
     return p
+
+
+def _kinetic(p):
+    """K^(k) = 1/2 sum_mu Tr (P_mu * P_mu)^(k) = 1/2 sum_mu sum_j Tr(P^(j) P^(k-j))."""
+    nord = p.shape[1]
+    kin = np.zeros(nord)
+    for mu in range(4):
+        for kk in range(nord):
+            for j in range(kk + 1):
+                kin[kk] += 0.5 * np.sum(p[mu, j] * p[mu, kk - j].T).real
+    return kin
+
+
+@pytest.mark.parametrize("L,k,nt", [(9, 2, 15), (15, 4, 15)])
+def test_energy_error_scales_as_dt_squared_on_gpu(L, k, nt):
+    # series Hamiltonian from the library's own action and the momenta;
+    # fixed trajectory length, half the step: the error drops by about 4
+    u = series_links(L, k, nt, 0.5, 9)
+    eta = synth.langevin_noise(synth.rng_for(953, L), 1, L * L)
+    prm = pm.nspt_params(L, k, nt, 0.01)
+    p0 = _refresh_all(eta[0], nt)
+    h0 = pm.nspt_action(to_dev(u), prm).cpu().numpy()[0] + _kinetic(p0)
+    dh = []
+    for ns in (4, 8):
+        gu, gp = _gpu_traj(u, eta, L, k, nt, 0.2 / ns, ns)
+        h = pm.nspt_action(to_dev(gu), prm).cpu().numpy()[0] + _kinetic(gp[0])
+        dh.append(h - h0)
+    ratios = np.array([dh[0][kk] / dh[1][kk] for kk in (2, 3, 4)])
+    print(f"N={L * L}: energy error ratios (orders 2-4) {ratios}")
+    assert np.all((ratios > 3.5) & (ratios < 4.5)), ratios
+
+
+def _refresh_all(eta_r, nt):
+    return np.stack([_refresh(eta_r[mu], nt) for mu in range(4)])
