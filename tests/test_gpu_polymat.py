@@ -109,7 +109,7 @@ def test_batched_uneven_with_conjugated_operands():
         assert e.max() < TOL["fp64"], e
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("n", [17, 33, 81, 161, 193, 225, 289])
 def test_thin_edge_sizes_all_operand_forms(prec, n):
     """n = 16 m + 1: the last row and column of each mode product take the
