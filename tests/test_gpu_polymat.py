@@ -213,3 +213,24 @@ def test_short_series_dispatch_and_alias_fallback(nt):
     da, db = to_dev(a), to_dev(b)
     pm.polymat_mul(da, db, C=da)
     assert order_errors(to_host(da), ref).max() < TOL["fp64"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_maximum_matrix_size_sampled(prec):
+    # N = PM_MAX_N: every index of the kernels and the workspace at its largest;
+    # checked on sampled entries computed one by one from eq. (5)
+    n, nt = 4096, 1
+    rng = np.random.default_rng(4096)
+    a = to_dev(synth.random_series(synth.rng_for(40, 0), n, nt, 0.5))
+    b = to_dev(synth.random_series(synth.rng_for(40, 1), n, nt, 0.5))
+    items = [dict(A=a, B=b, C=torch.empty_like(a))]
+    pm.polymat_mul_batched(items, precision=prec)
+    c = items[0]["C"]
+    ks, iis, jjs = rng.integers(0, nt + 1, 48), rng.integers(0, n, 48), rng.integers(0, n, 48)
+    got = c[torch.as_tensor(ks, device=DEV), torch.as_tensor(iis, device=DEV), torch.as_tensor(jjs, device=DEV)]
+    got = got.cpu().numpy()
+    for t, (k, i, j) in enumerate(zip(ks, iis, jjs)):
+        terms = [(a[l, i, :].cpu().numpy(), b[k - l, :, j].cpu().numpy()) for l in range(k + 1)]
+        ref = sum(np.dot(x, y) for x, y in terms)
+        scale = sum(np.linalg.norm(x) * np.linalg.norm(y) for x, y in terms)
+        assert abs(got[t] - ref) <= TOL[prec] * scale, (prec, k, i, j, got[t], ref)
