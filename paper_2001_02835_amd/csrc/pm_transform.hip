@@ -114,12 +114,6 @@ __global__ __launch_bounds__(256) void k_norms(NormArgs args) {
 constexpr double kAbsent = 1e300;
 constexpr double kNoiseFloor = 1e-15;
 
-__device__ __forceinline__ double lane_value(double v, int src) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
-  return __hiloint2double(hi, lo);
-}
-
 __global__ __launch_bounds__(64) void k_scale(ScaleArgs args) {
   const ScaleJob& jb = args.jobs[blockIdx.x];
   const int nord = jb.nord;
@@ -154,15 +148,19 @@ __global__ __launch_bounds__(64) void k_scale(ScaleArgs args) {
     }
     if (na < kNoiseFloor * ma) na = 0.0;
     if (nb < kNoiseFloor * mb) nb = 0.0;
-    // c_m = sum_j a_j b_{m-j}: lane m holds c_m (m < 64) and c_{m+64}
+    // c_m = sum_j a_j b_{m-j}: lane m holds c_m (m < 64) and c_{m+64}; the
+    // norms go through LDS so that the iterations do not wait on each other
+    __shared__ double a_s[64], b_s[64];
+    a_s[tid] = na;
+    b_s[tid] = nb;
+    __syncthreads();
     double c0 = 0.0, c1 = 0.0;
     const int nm = 2 * nord - 1;
     for (int j = 0; j < nord; ++j) {
-      const double aj = lane_value(na, j);
+      const double aj = a_s[j];
       const int m0 = tid - j, m1 = tid + 64 - j;
-      // b_{m-j}: fetch from lane (m - j) when it is a valid order
-      const double b0 = __shfl(nb, m0 >= 0 && m0 < nord ? m0 : 0);
-      const double b1 = __shfl(nb, m1 >= 0 && m1 < nord ? m1 : 0);
+      const double b0 = b_s[m0 >= 0 && m0 < nord ? m0 : 0];
+      const double b1 = b_s[m1 >= 0 && m1 < nord ? m1 : 0];
       if (m0 >= 0 && m0 < nord) c0 = fma(aj, b0, c0);
       if (m1 >= 0 && m1 < nord && tid + 64 < nm) c1 = fma(aj, b1, c1);
     }
@@ -185,6 +183,7 @@ __global__ __launch_bounds__(64) void k_scale(ScaleArgs args) {
         const double tt = lo + step * tid;
         // four independent max / min chains over m
         double mx[4] = {-kAbsent, -kAbsent, -kAbsent, -kAbsent}, mn[4] = {kAbsent, kAbsent, kAbsent, kAbsent};
+#pragma unroll 2
         for (int m = 0; m < 64; m += 4) {
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
@@ -192,7 +191,14 @@ __global__ __launch_bounds__(64) void k_scale(ScaleArgs args) {
             mn[u] = fmin(mn[u], fma(static_cast<double>(m + u), tt, lmin_s[m + u]));
           }
         }
-        for (int m = 64; m < nm; ++m) mx[m & 3] = fmax(mx[m & 3], fma(static_cast<double>(m), tt, lmax_s[m]));
+        // orders 64..nm-1 (present only when nord > 32; the absent ones read -kAbsent)
+        if (nm > 64) {
+#pragma unroll 2
+          for (int m = 64; m < 128; m += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) mx[u] = fmax(mx[u], fma(static_cast<double>(m + u), tt, lmax_s[m + u]));
+          }
+        }
         // arg-min over lanes; near-ties (a flat objective, e.g. only one
         // nonzero order) go to the candidate closest to t = 0 (s = 1)
         double f = fmax(fmax(mx[0], mx[1]), fmax(mx[2], mx[3])) - fmin(fmin(mn[0], mn[1]), fmin(mn[2], mn[3]));
