@@ -1,6 +1,7 @@
 /*
  * polymat.h - C ABI of the MI355X FFT-CONV library for truncated matrix power
- * series and the NSPT Euler-Langevin step of the twisted Eguchi-Kawai model
+ * series and the NSPT updates (Euler-Langevin step, leapfrog molecular-
+ * dynamics trajectory) and action series of the twisted Eguchi-Kawai model
  * (arXiv:2001.02835).
  *
  * Series layout (all entry points): a truncated power series in g whose
@@ -19,13 +20,17 @@
  * aligned, not overlapping any operand), sized by the matching *_size query.
  * A device fault surfaces as PM_ERR_DEVICE on a later call or at the
  * caller's synchronisation.  No C++ exception crosses this interface.
+ * Calls enqueue kernel launches only (no memset or copy), so a call can be
+ * captured into a HIP graph and replayed (with phase timing off).
  * Host-side state (none beyond constants) is thread-safe; calls that share
  * one workspace must be ordered on one stream.
  *
  * Precision modes (the per-frequency products only; the transforms, their
  * twiddles and 1/L normalisation, the rescaling and every value stored in a
  * caller's series are FP64):
- *   PM_PREC_FP64   - FP64 MFMA products (4 real products per complex one).
+ *   PM_PREC_FP64   - FP64 MFMA products (the three-real-product form of a
+ *                    complex product; the environment variable
+ *                    POLYMAT_GEMM_4M=1 selects the four-product form).
  *   PM_PREC_FP32   - Fourier coefficients rounded to FP32, FP32 MFMA products
  *                    with FP32 accumulation.
  *   PM_PREC_BF16X3 - Fourier coefficients split as hi + lo with hi, lo BF16;
