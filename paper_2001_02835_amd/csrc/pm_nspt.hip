@@ -28,6 +28,7 @@
 //    by Horner in Y^b; B_q is added inside the re-truncation of each link.
 //  link update
 //    U_m <- E_m * U_m, order 0 left as it is (E^(0) = 1 exactly).
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -41,6 +42,7 @@ namespace pm {
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kMaxNtruncPlus1 = PM_MAX_NTRUNC + 1;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 bool valid_params(int replicas, const nspt_params* p, int prec) {
@@ -58,11 +60,44 @@ int tlength(int ntrunc) {
   return L;
 }
 
-int ps_block(int ntrunc) {
-  int b = 1;
-  while (b * b < ntrunc + 1) ++b;
-  return b;
+// Paterson-Stockmeyer plan of exp(Y) for Y = O(g): powers Y^2..Y^b at the
+// full length L, then Horner in Y^b, Z_Q = B_Q, Z_q = Y^b * Z_{q+1} + B_q
+// (Q = ntrunc / b).  Z_q is needed only to order K_q = ntrunc - q b (it is
+// multiplied by (Y^b)^q = O(g^{q b}) afterwards), so the product of step q
+// runs at the length of order K_q, made at most half the next step's
+// length (the re-truncation between two steps at most doubles the length).
+// L of 128 keeps one length throughout.
+struct ExpPlan {
+  int b, Q;
+  int len[kMaxNtruncPlus1];   // len[q]: transform length of the product of Horner step q (q < Q)
+};
+
+int tlength(int ntrunc);
+
+ExpPlan exp_plan(int ntrunc) {
+  const int L = tlength(ntrunc);
+  ExpPlan best{};
+  long best_cost = -1;
+  for (int b = 1; b <= 12; ++b) {
+    ExpPlan pl{};
+    pl.b = b;
+    pl.Q = ntrunc / b;
+    long cost = static_cast<long>(b - 1) * L;
+    for (int q = 0; q < pl.Q; ++q) {
+      int lq = L;
+      if (L <= 64 && q > 0) {
+        lq = tlength(ntrunc - q * b);
+        if (lq < pl.len[q - 1] / 2) lq = pl.len[q - 1] / 2;
+      }
+      pl.len[q] = lq;
+      cost += lq;
+    }
+    if (best_cost < 0 || cost < best_cost) { best = pl; best_cost = cost; }
+  }
+  return best;
 }
+
+int ps_block(int ntrunc) { return exp_plan(ntrunc).b; }
 
 FourierType in_type(int prec) { return prec == PM_PREC_FP64 ? kF64 : (prec == PM_PREC_FP32 ? kF32 : kBF16Split); }
 FourierType out_type(int prec) { return prec == PM_PREC_FP64 ? kF64 : kF32; }
@@ -155,6 +190,7 @@ struct RetruncBatch {
   const Layout* l;
   FourierType fin, fout;
   hipStream_t s;
+  int lin = 0, lout = 0, nord = 0;   // 0: the call's L and order count
   RetruncArgs a{};
   pm_status status = PM_OK;
   void add(const void* src, void* dst, double2* tdst, const double2* addbase, size_t add_stride) {
@@ -168,11 +204,12 @@ struct RetruncBatch {
     j.add_stride = add_stride;
     j.E = l->E;
     j.n = l->n;
-    j.nord = l->nord;
+    j.nord = nord ? nord : l->nord;
   }
   void flush() {
     if (status || a.njobs == 0) return;
-    status = st(timed(PM_PHASE_RETRUNC, s, [&] { return launch_retrunc(a, l->L, l->E, fin, fout, s); }));
+    const int li = lin ? lin : l->L, lo = lout ? lout : l->L;
+    status = st(timed(PM_PHASE_RETRUNC, s, [&] { return launch_retrunc(a, li, lo, l->E, fin, fout, s); }));
     a.njobs = 0;
   }
 };
@@ -592,10 +629,12 @@ struct Run {
       rt.flush();
       if (rt.status) return rt.status;
     }
-    // E = sum_q (Y^b)^q B_q(Y) by Horner in Y^b
+    // E = sum_q (Y^b)^q B_q(Y) by Horner in Y^b, each step at the length
+    // of the orders it still needs (ExpPlan)
     {
       const int nt = nord - 1;
-      const int Q = nt / b;
+      const ExpPlan pl = exp_plan(nt);
+      const int Q = pl.Q;
       auto cfac = [&](int jj) {
         if (jj > nt) return 0.0;
         double f = 1.0;
@@ -603,15 +642,56 @@ struct Run {
         return 1.0 / f;
       };
       const size_t ystride = l.tser / sizeof(double2);   // elements between Y^i and Y^(i+1)
+      // Y^b at every shorter length in use (G slots 4.. are free after the
+      // staples): truncated at L'/2 - 1 orders, so no product wraps around
+      int nshort = 0, shortlen[8];
+      for (int q = 0; q < Q; ++q) {
+        const int lq = pl.len[q];
+        bool seen = lq == L;
+        for (int i = 0; i < nshort; ++i) seen = seen || shortlen[i] == lq;
+        if (!seen) shortlen[nshort++] = lq;
+      }
+      auto ybf = [&](int r, int m, int lq) -> const void* {
+        if (lq == L) return Ypf(r, m, b);
+        for (int i = 0; i < nshort; ++i)
+          if (shortlen[i] == lq) return G(r, 4 + 4 * i + m);
+        return nullptr;
+      };
+      for (int i = 0; i < nshort; ++i) {
+        FwdArgs fw{};
+        auto flush = [&]() -> pm_status {
+          pm_status e = st(timed(PM_PHASE_FORWARD, s, [&] { return launch_forward(fw, shortlen[i], E, fin, s); }));
+          fw.njobs = 0;
+          return e;
+        };
+        for (int r = 0; r < R; ++r)
+          for (int m = 0; m < 4; ++m) {
+            if (fw.njobs == kMaxTransformJobs) { pm_status e = flush(); if (e) return e; }
+            FwdJob& j = fw.jobs[fw.njobs++];
+            j.src = Ypt(r, m, b);
+            j.dst = G(r, 4 + 4 * i + m);
+            j.rec = unit;
+            j.E = E;
+            j.nord = std::min(nord, shortlen[i] / 2);
+            j.n = n;
+          }
+        pm_status e = flush();
+        if (e) return e;
+      }
       for (int q = Q; q >= 0; --q) {
+        const int lprod = q < Q ? pl.len[q] : 0;             // length of this step's product
+        const int lnext = q > 0 ? pl.len[q - 1] : L;          // length the result is transformed at
         if (q < Q) {
           GemmBatch g{fin, s, 0};
           for (int r = 0; r < R; ++r)
-            for (int m = 0; m < 4; ++m) g.add(Ypf(r, m, b), Zf(r, m), G(r, m), n, L);
+            for (int m = 0; m < 4; ++m) g.add(ybf(r, m, lprod), Zf(r, m), G(r, m), n, lprod);
           g.flush();
           if (g.status) return g.status;
         }
         RetruncBatch rt{&l, fout, fin, s};
+        rt.lin = q < Q ? lprod : lnext;
+        rt.lout = lnext;
+        rt.nord = std::min(nord, nt - q * b + 1);
         rt.a.nadd = b - 1;
         for (int i = 1; i < b; ++i) rt.a.coef[i - 1] = make_double2(cfac(q * b + i), 0.0);
         rt.a.idcoef = make_double2(cfac(q * b), 0.0);

@@ -98,8 +98,10 @@ struct SeriesScaleJob {
 constexpr int kMaxSeriesScaleJobs = 64;
 struct SeriesScaleArgs { SeriesScaleJob jobs[kMaxSeriesScaleJobs]; int njobs; };
 
-hipError_t launch_retrunc(const RetruncArgs& a, int L, int max_entries, FourierType fin, FourierType fout,
-                          hipStream_t s);
+// lin: transform length of the products being re-truncated; lout: length of
+// the forward transform written (lout == lin, or 2 lin for lin <= 32).
+hipError_t launch_retrunc(const RetruncArgs& a, int lin, int lout, int max_entries, FourierType fin,
+                          FourierType fout, hipStream_t s);
 hipError_t launch_inv_combine(const CombineArgs& a, int L, int max_entries, FourierType fin, hipStream_t s);
 hipError_t launch_trace(const TraceArgs& a, int max_nord, hipStream_t s);
 hipError_t launch_force(const ForceArgs& a, int n, int max_nord, hipStream_t s);

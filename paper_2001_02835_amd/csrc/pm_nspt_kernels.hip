@@ -30,8 +30,12 @@ namespace {
 
 // ----------------------------------------------------------- re-truncation
 
-template <int L, FourierType FIN, FourierType FOUT>
-__global__ __launch_bounds__(kFftThreads, fft_min_waves<L>()) void k_retrunc(RetruncArgs args) {
+// LIN: length of the product's transform; LOUT: length of the forward
+// transform of the result (LOUT >= LIN, both with the same lanes per entry).
+template <int LIN, int LOUT, FourierType FIN, FourierType FOUT>
+__global__ __launch_bounds__(kFftThreads, fft_min_waves<LOUT>()) void k_retrunc(RetruncArgs args) {
+  static_assert(LOUT >= LIN && fft_ent<LIN>() == fft_ent<LOUT>(), "unsupported length pair");
+  constexpr int L = LOUT;
   constexpr int ENT = fft_ent<L>();
   constexpr int KSTEP = kFftThreads / ENT;
   __shared__ double2 acc[L / 2][ENT];
@@ -47,7 +51,7 @@ __global__ __launch_bounds__(kFftThreads, fft_min_waves<L>()) void k_retrunc(Ret
   const int nord = jb.nord;
   if (jb.src) {
     auto load = [&](int p) { return valid ? load_mode<FIN>(jb.src, E, p, e) : make_double2(0.0, 0.0); };
-    inverse_to_lds<L>(load, acc, lane, r);
+    inverse_to_lds<LIN>(load, acc, lane, r);
   }
   // time-domain value of order k: (1/L) inverse + addends (+ identity at order 0)
   const int n = jb.n;
@@ -57,7 +61,7 @@ __global__ __launch_bounds__(kFftThreads, fft_min_waves<L>()) void k_retrunc(Ret
       acc[k][el] = make_double2(0.0, 0.0);
       continue;
     }
-    double2 x = jb.src ? cscale(acc[k][el], 1.0 / L) : make_double2(0.0, 0.0);
+    double2 x = jb.src ? cscale(acc[k][el], 1.0 / LIN) : make_double2(0.0, 0.0);
     if (valid) {
       for (int a = 0; a < args.nadd; ++a) {
         const double2 y = jb.add[static_cast<size_t>(a) * jb.add_stride + static_cast<size_t>(k) * E + e];
@@ -229,17 +233,16 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs args) {
 }
 
 template <FourierType FIN, FourierType FOUT>
-hipError_t retrunc_dispatch(const RetruncArgs& a, int L, dim3 g, hipStream_t s) {
-  switch (L) {
-    case 4: k_retrunc<4, FIN, FOUT><<<g, kFftThreads, 0, s>>>(a); break;
-    case 8: k_retrunc<8, FIN, FOUT><<<g, kFftThreads, 0, s>>>(a); break;
-    case 16: k_retrunc<16, FIN, FOUT><<<g, kFftThreads, 0, s>>>(a); break;
-    case 32: k_retrunc<32, FIN, FOUT><<<g, kFftThreads, 0, s>>>(a); break;
-    case 64: k_retrunc<64, FIN, FOUT><<<g, kFftThreads, 0, s>>>(a); break;
-    case 128: k_retrunc<128, FIN, FOUT><<<g, kFftThreads, 0, s>>>(a); break;
-    default: return hipErrorInvalidValue;
+hipError_t retrunc_dispatch(const RetruncArgs& a, int lin, int lout, dim3 g, hipStream_t s) {
+#define PM_RT(A, B)                                                     \
+  if (lin == A && lout == B) {                                          \
+    k_retrunc<A, B, FIN, FOUT><<<g, kFftThreads, 0, s>>>(a);            \
+    return hipGetLastError();                                           \
   }
-  return hipGetLastError();
+  PM_RT(4, 4) PM_RT(8, 8) PM_RT(16, 16) PM_RT(32, 32) PM_RT(64, 64) PM_RT(128, 128)
+  PM_RT(4, 8) PM_RT(8, 16) PM_RT(16, 32) PM_RT(32, 64)
+#undef PM_RT
+  return hipErrorInvalidValue;
 }
 
 template <FourierType FIN, int NSRC>
@@ -258,14 +261,14 @@ hipError_t combine_dispatch(const CombineArgs& a, int L, dim3 g, hipStream_t s) 
 
 }  // namespace
 
-hipError_t launch_retrunc(const RetruncArgs& a, int L, int max_entries, FourierType fin, FourierType fout,
-                          hipStream_t s) {
+hipError_t launch_retrunc(const RetruncArgs& a, int lin, int lout, int max_entries, FourierType fin,
+                          FourierType fout, hipStream_t s) {
   if (a.njobs <= 0) return hipSuccess;
-  const int ent = fft_entries_per_group(L);
+  const int ent = fft_entries_per_group(lout);
   dim3 g((max_entries + ent - 1) / ent, a.njobs);
-  if (fin == kF64) return retrunc_dispatch<kF64, kF64>(a, L, g, s);
-  if (fout == kF32) return retrunc_dispatch<kF32, kF32>(a, L, g, s);
-  return retrunc_dispatch<kF32, kBF16Split>(a, L, g, s);
+  if (fin == kF64) return retrunc_dispatch<kF64, kF64>(a, lin, lout, g, s);
+  if (fout == kF32) return retrunc_dispatch<kF32, kF32>(a, lin, lout, g, s);
+  return retrunc_dispatch<kF32, kBF16Split>(a, lin, lout, g, s);
 }
 
 hipError_t launch_inv_combine(const CombineArgs& a, int L, int max_entries, FourierType fin, hipStream_t s) {
