@@ -146,3 +146,47 @@ def test_trajectory_is_gauge_covariant():
     u2, p2 = nspt.md_trajectory(rot(u), rot(p), z, 0.2, 2)
     assert np.abs(u2 - rot(u1)).max() < 1e-12
     assert np.abs(p2 - rot(p1)).max() < 1e-11
+
+
+def _dense_wilson(u, z, a, b):
+    n = u.shape[-1]
+    w = 0.0
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            x = (np.linalg.matrix_power(u[mu], a) @ np.linalg.matrix_power(u[nu], b)
+                 @ np.linalg.matrix_power(u[mu].conj().T, a) @ np.linalg.matrix_power(u[nu].conj().T, b))
+            w += (z[mu, nu] ** (a * b) * np.trace(x)).real
+    return w / (6 * n)
+
+
+def test_plaquette_is_the_action():
+    L, k, nt = 3, 1, 5
+    u = _series_links(L, k, nt, 0.6, 11)
+    z = tek.twist_tensor(L, k)
+    w = nspt.wilson_loop_series(u, z, 1, 1)
+    s = nspt.series_action(u, z)
+    ref = -s / (12 * L * L)
+    ref[0] += 1.0
+    assert np.abs(w - ref).max() < 1e-13
+
+
+@pytest.mark.parametrize("a,b", [(1, 1), (1, 2), (2, 2), (2, 3)])
+def test_wilson_loops_are_one_at_the_vacuum(a, b):
+    L, k, nt = 5, 2, 4
+    u = synth.vacuum_links(L, k, nt)[0]
+    w = nspt.wilson_loop_series(u, tek.twist_tensor(L, k), a, b)
+    assert abs(w[0] - 1.0) < 1e-13 and np.abs(w[1:]).max() < 1e-13
+
+
+@pytest.mark.parametrize("a,b", [(1, 2), (2, 2), (2, 3)])
+def test_wilson_loop_series_is_the_taylor_expansion_of_the_dense_loop(a, b):
+    # small g: the remainder is in its leading O(g^(nt+1)) regime
+    L, k, nt = 3, 1, 4
+    u = _series_links(L, k, nt, 0.3, 12)
+    z = tek.twist_tensor(L, k)
+    w = nspt.wilson_loop_series(u, z, a, b)
+    errs = []
+    for g in (0.01, 0.02):
+        dense = np.stack([sum(g ** kk * u[mu, kk] for kk in range(nt + 1)) for mu in range(4)])
+        errs.append(abs(_dense_wilson(dense, z, a, b) - sum(g ** kk * w[kk] for kk in range(nt + 1))))
+    assert errs[1] / errs[0] > 0.6 * 2 ** (nt + 1)
