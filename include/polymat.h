@@ -299,6 +299,24 @@ pm_status nspt_action(const void* U, int replicas, const nspt_params* params,
                       int precision, double* S, void* workspace,
                       size_t workspace_bytes, void* stream);
 
+/*
+ * nspt_wilson_loop - the a x b Wilson loop of the reduced model as a series
+ * in g (the observable whose perturbative coefficients the paper computes,
+ * abstract and Section 1), averaged over the six planes:
+ *   W^(k) = 1/(6N) sum_{mu<nu} Re z_{mu nu}^{ab} Tr (U_mu^a * U_nu^b * (U_mu^+)^a * (U_nu^+)^b)^(k),
+ * with z_{mu nu}^{ab} = exp(2 pi i k a b / L) for mu < nu, so that W = 1 at the
+ * twisted vacuum; W(1, 1) = 1 - S / (12 N) with S the series of nspt_action.
+ *   U     device complex128 [replicas][4][ntrunc+1][n][n] (read only).
+ *   a, b  loop sides, 1 .. 4.
+ *   W     device float64 [replicas][ntrunc+1], written.
+ * precision applies to the products.  The workspace is the one of
+ * nspt_langevin_step (nspt_workspace_size); U, W and the workspace must not
+ * overlap (PM_ERR_INVALID).
+ */
+pm_status nspt_wilson_loop(const void* U, int replicas, const nspt_params* params,
+                           int a, int b, int precision, double* W, void* workspace,
+                           size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,6 +60,7 @@ SIGNATURES = {
     "nspt_langevin_step": (_I, [_VP, _VP, _I, ctypes.POINTER(NsptParams), _I, _VP, _SZ, _VP]),
     "polymat_mul_naive": (_I, [_VP, _VP, _VP, _I, _I, _I, _I, _VP]),
     "nspt_action": (_I, [_VP, _I, ctypes.POINTER(NsptParams), _I, _VP, _VP, _SZ, _VP]),
+    "nspt_wilson_loop": (_I, [_VP, _I, ctypes.POINTER(NsptParams), _I, _I, _I, _VP, _VP, _SZ, _VP]),
     "nspt_md_trajectory": (_I, [_VP, _VP, _VP, _I, ctypes.POINTER(NsptParams), _I, _I, _VP, _SZ, _VP]),
 }
 

@@ -225,6 +225,24 @@ def nspt_action(U: torch.Tensor, params: nat.NsptParams, precision="fp64",
     return S
 
 
+def nspt_wilson_loop(U: torch.Tensor, params: nat.NsptParams, a: int, b: int, precision="fp64",
+                     ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """a x b Wilson-loop series W^(k) (float64 [R, ntrunc+1]) of link series U [R, 4, ntrunc+1, n, n]."""
+    _series_check(U, "U")
+    R, nord = U.shape[0], U.shape[2]
+    p = _prec(precision)
+    need = nat.lib().nspt_workspace_size(R, ctypes.byref(params), p)
+    if need == 0:
+        raise ValueError("invalid NSPT parameters")
+    if ws is None:
+        ws = workspace(need, U.device)
+    W = torch.empty((R, nord), dtype=torch.float64, device=U.device)
+    st = nat.lib().nspt_wilson_loop(U.data_ptr(), R, ctypes.byref(params), int(a), int(b), p, W.data_ptr(),
+                                    ws.data_ptr(), ws.numel(), _stream_ptr(U.device))
+    nat.check(st, "nspt_wilson_loop")
+    return W
+
+
 def timing_enable(on: bool = True) -> None:
     """Bracket every library launch with HIP events (for measurement only)."""
     nat.check(nat.lib().polymat_timing_enable(1 if on else 0), "polymat_timing_enable")

@@ -485,9 +485,93 @@ struct Run {
       pm_status e = flush();
       if (e) return e;
     }
+    return traces_to(S, 12.0 * n, -2.0);
+  }
+
+  // ---- a x b Wilson loops W^(k) = 1/(6N) sum_{m<n} Re z_mn^{ab}
+  //      Tr (U_m^a U_n^b (U_m^+)^a (U_n^+)^b)^(k) into W [R][nord]; the loop of
+  //      plane (m, n) is A * B^+ with A = U_m^a U_n^b and B = U_n^b U_m^a
+  pm_status wilson(int wa, int wb, double* W) {
+    const int n = l.n, E = l.E, nord = l.nord, L = l.L;
+    const int jmax = std::max(wa, wb);
+    // powers U^j (j <= 4) in Fourier space: Xt slots 12 + 4 (j - 2) + m
+    auto pw = [&](int r, int m, int j) -> const void* { return j == 1 ? Ut(r, m) : Xt(r, 12 + 4 * (j - 2) + m); };
+    for (int j = 2; j <= jmax; ++j) {
+      GemmBatch g{fin, s, 0};
+      for (int r = 0; r < R; ++r)
+        for (int m = 0; m < 4; ++m) g.add(pw(r, m, j - 1), Ut(r, m), G(r, m), n, L);
+      g.flush();
+      if (g.status) return g.status;
+      RetruncBatch rt{&l, fout, fin, s};
+      rt.a.nadd = 0;
+      rt.a.idcoef = make_double2(0.0, 0.0);
+      for (int r = 0; r < R; ++r)
+        for (int m = 0; m < 4; ++m) rt.add(G(r, m), Xt(r, 12 + 4 * (j - 2) + m), nullptr, nullptr, 0);
+      rt.flush();
+      if (rt.status) return rt.status;
+    }
+    // A_mn = U_m^a U_n^b into slot (m, n), B_mn = U_n^b U_m^a into slot (n, m), m < n
+    {
+      GemmBatch g{fin, s, 0};
+      for (int r = 0; r < R; ++r)
+        for (int m = 0; m < 4; ++m)
+          for (int q = m + 1; q < 4; ++q) {
+            g.add(pw(r, m, wa), pw(r, q, wb), G(r, qslot[m][q]), n, L);
+            g.add(pw(r, q, wb), pw(r, m, wa), G(r, qslot[q][m]), n, L);
+          }
+      g.flush();
+      if (g.status) return g.status;
+      RetruncBatch rt{&l, fout, fin, s};
+      rt.a.nadd = 0;
+      rt.a.idcoef = make_double2(0.0, 0.0);
+      for (int r = 0; r < R; ++r)
+        for (int slot = 0; slot < 12; ++slot) rt.add(G(r, slot), Xt(r, slot), nullptr, nullptr, 0);
+      rt.flush();
+      if (rt.status) return rt.status;
+      GemmBatch nc{fin, s, 1};
+      for (int r = 0; r < R; ++r)
+        for (int m = 0; m < 4; ++m)
+          for (int q = m + 1; q < 4; ++q) nc.add(Xt(r, qslot[m][q]), Xt(r, qslot[q][m]), G(r, pair[m][q]), n, L);
+      nc.flush();
+      if (nc.status) return PM_ERR_DEVICE;
+    }
+    {
+      CombineArgs ca{};
+      auto flush = [&]() -> pm_status {
+        if (ca.njobs == 0) return PM_OK;
+        pm_status e = st(timed(PM_PHASE_INVERSE, s, [&] { return launch_inv_combine(ca, L, E, fout, s); }));
+        ca.njobs = 0;
+        return e;
+      };
+      const double ang = 2.0 * M_PI * p->k * wa * wb / p->L;   // z^{ab} for m < n
+      for (int r = 0; r < R; ++r) {
+        if (ca.njobs == kMaxCombineJobs) { pm_status e = flush(); if (e) return e; }
+        CombineJob& j = ca.jobs[ca.njobs++];
+        j.nsrc = 0;
+        for (int m = 0; m < 4; ++m)
+          for (int q = m + 1; q < 4; ++q) {
+            j.src[j.nsrc] = G(r, pair[m][q]);
+            j.coef[j.nsrc++] = make_double2(std::cos(ang), std::sin(ang));
+          }
+        j.dst = Mser(r, 0);
+        j.rec = rec;
+        j.E = E;
+        j.nord = nord;
+        j.kmin = 0;
+      }
+      pm_status e = flush();
+      if (e) return e;
+    }
+    return traces_to(W, 0.0, 1.0 / (6.0 * n));
+  }
+
+  // out[r][k] = c0 delta_k0 + c1 Re Tr Mser(r, 0)^(k)
+  pm_status traces_to(double* out, double c0, double c1) {
+    const int n = l.n, nord = l.nord;
     TraceArgs ta{};
     ActionArgs aa{};
-    aa.n = n;
+    aa.c0 = c0;
+    aa.c1 = c1;
     aa.nord = nord;
     for (int r = 0; r < R; ++r) {
       if (ta.njobs == kMaxTransformJobs) {
@@ -504,7 +588,7 @@ struct Run {
     pm_status e = st(timed(PM_PHASE_OTHER, s, [&] { return launch_trace(ta, nord, s); }));
     if (e) return e;
     aa.tr = trc;
-    aa.S = S;
+    aa.S = out;
     aa.count = R * nord;
     return st(timed(PM_PHASE_OTHER, s, [&] { return launch_action(aa, s); }));
   }
@@ -800,6 +884,25 @@ pm_status nspt_series_action(const void* U, int R, const nspt_params* p, int pre
   Run run(const_cast<void*>(U), R, p, prec, workspace, s);   // U is only read
   pm_status e = run.links_forward();
   if (!e) e = run.action(S);
+  return e;
+}
+
+pm_status nspt_wilson(const void* U, int R, const nspt_params* p, int wa, int wb, int prec, double* W,
+                      void* workspace, size_t workspace_bytes, hipStream_t s) {
+  if (!valid_params(R, p, prec)) return PM_ERR_INVALID;
+  if (wa < 1 || wa > 4 || wb < 1 || wb > 4) return PM_ERR_INVALID;
+  if (!U || !W || !workspace) return PM_ERR_INVALID;
+  if (reinterpret_cast<uintptr_t>(U) % 16 || reinterpret_cast<uintptr_t>(W) % 8 ||
+      reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return PM_ERR_INVALID;
+  const Layout l = layout(R, p, prec);
+  if (workspace_bytes < l.total) return PM_ERR_WORKSPACE;
+  const size_t ub = static_cast<size_t>(R) * 4 * l.nord * l.E * 16, wbytes = static_cast<size_t>(R) * l.nord * 8;
+  if (overlaps(workspace, l.total, U, ub) || overlaps(workspace, l.total, W, wbytes) || overlaps(U, ub, W, wbytes))
+    return PM_ERR_INVALID;
+  Run run(const_cast<void*>(U), R, p, prec, workspace, s);   // U is only read
+  pm_status e = run.links_forward();
+  if (!e) e = run.wilson(wa, wb, W);
   return e;
 }
 

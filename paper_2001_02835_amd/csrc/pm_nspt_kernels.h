@@ -85,8 +85,8 @@ constexpr int kMaxRefreshJobs = 64;
 struct RefreshArgs { RefreshJob jobs[kMaxRefreshJobs]; int njobs; };
 constexpr int kMaxMdSteps = 100000;
 
-// S[i] = 12 n delta_{k0} - 2 Re tr[i], k = i mod nord (action series).
-struct ActionArgs { const double2* tr; double* S; int n; int nord; int count; };
+// S[i] = c0 delta_{k0} + c1 Re tr[i], k = i mod nord (action or Wilson-loop series).
+struct ActionArgs { const double2* tr; double* S; double c0; double c1; int nord; int count; };
 
 // x^(k) <- s^k x^(k) in place (order k of a [nord][E] series).
 struct SeriesScaleJob {

@@ -17,7 +17,7 @@
 //                     s^k for the following products.
 //  * k_refresh      - momentum refresh, P^(1) = eta and all other orders zero.
 //  * k_series_scale - x^(k) <- s^k x^(k) in place.
-//  * k_action       - action series from the traces of the plaquette sum.
+//  * k_action       - action or Wilson-loop series from the traces of a loop sum.
 //
 // All series here are FP64 complex [nord][n][n]; Fourier coefficients use the
 // formats of the product kernels (FP64, FP32 or split BF16).
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void k_action(ActionArgs args) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= args.count) return;
   const int k = i % args.nord;
-  args.S[i] = (k == 0 ? 12.0 * args.n : 0.0) - 2.0 * args.tr[i].x;
+  args.S[i] = (k == 0 ? args.c0 : 0.0) + args.c1 * args.tr[i].x;
 }
 
 // ------------------------------------------------------------------ trace

@@ -567,6 +567,12 @@ pm_status nspt_action(const void* U, int replicas, const nspt_params* params, in
                                 static_cast<hipStream_t>(stream));
 }
 
+pm_status nspt_wilson_loop(const void* U, int replicas, const nspt_params* params, int a, int b, int precision,
+                           double* W, void* workspace, size_t workspace_bytes, void* stream) {
+  return pm::nspt_wilson(U, replicas, params, a, b, precision, W, workspace, workspace_bytes,
+                         static_cast<hipStream_t>(stream));
+}
+
 pm_status nspt_md_trajectory(void* U, void* P, const void* eta, int replicas, const nspt_params* params,
                              int nsteps, int precision, void* workspace, size_t workspace_bytes,
                              void* stream) {

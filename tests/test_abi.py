@@ -176,3 +176,15 @@ def test_action_rejects_bad_arguments():
     assert lib.nspt_action(FAKE_A, 1, ctypes.byref(good), 0, S, FAKE_WS, need - 1, None) == nat.PM_ERR_WORKSPACE
     assert lib.nspt_action(FAKE_A, 1, ctypes.byref(good), 0, FAKE_A, FAKE_WS, need, None) == nat.PM_ERR_INVALID
     assert lib.nspt_action(FAKE_A, 0, ctypes.byref(good), 0, S, FAKE_WS, need, None) == nat.PM_ERR_INVALID
+
+
+def test_wilson_loop_rejects_bad_arguments():
+    lib = pm.lib()
+    good = nat.NsptParams(9, 3, 1, 7, 0.01)
+    need = lib.nspt_workspace_size(1, ctypes.byref(good), 0)
+    f = lambda a, b, W=FAKE_C, nb=need: lib.nspt_wilson_loop(FAKE_A, 1, ctypes.byref(good), a, b, 0, W, FAKE_WS, nb,
+                                                            None)
+    assert f(0, 1) == nat.PM_ERR_INVALID
+    assert f(1, 5) == nat.PM_ERR_INVALID
+    assert f(2, 2, W=None) == nat.PM_ERR_INVALID
+    assert f(2, 2, nb=need - 1) == nat.PM_ERR_WORKSPACE

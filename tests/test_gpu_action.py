@@ -58,3 +58,32 @@ def test_action_precisions(prec):
     ref = nspt.series_action(u[0], tek.twist_tensor(L, k))
     err = np.abs(got[0] - ref) / _scale(u[0])
     assert err.max() < TOL[prec], err
+
+
+@pytest.mark.parametrize("a,b", [(1, 1), (1, 2), (2, 2), (2, 3), (4, 1)])
+def test_wilson_loops_match_oracle(a, b):
+    L, k, nt, R = 5, 2, 7, 2
+    u = series_links(L, k, nt, 0.6, 47, replicas=R)
+    z = tek.twist_tensor(L, k)
+    got = pm.nspt_wilson_loop(to_dev(u), pm.nspt_params(L, k, nt, 0.01), a, b).cpu().numpy()
+    for r in range(R):
+        ref = nspt.wilson_loop_series(u[r], z, a, b)
+        # terms of W^(k) are bounded by the 4-fold norm convolution of the powers, / (6N) * sqrt(N)
+        err = np.abs(got[r] - ref)
+        assert err.max() < 1e-11 * max(1.0, np.abs(ref).max()), (r, err)
+
+
+def test_wilson_loops_at_the_vacuum_and_plaquette_relation():
+    L, k, nt = 15, 4, 31
+    u = synth.vacuum_links(L, k, nt, replicas=1)
+    prm = pm.nspt_params(L, k, nt, 0.01)
+    for a, b in [(1, 1), (2, 2), (3, 2)]:
+        w = pm.nspt_wilson_loop(to_dev(u), prm, a, b).cpu().numpy()[0]
+        assert abs(w[0] - 1.0) < 1e-12 and np.abs(w[1:]).max() < 1e-12, (a, b)
+    us = series_links(L, k, 15, 0.5, 48)
+    prm = pm.nspt_params(L, k, 15, 0.01)
+    w = pm.nspt_wilson_loop(to_dev(us), prm, 1, 1).cpu().numpy()[0]
+    s = pm.nspt_action(to_dev(us), prm).cpu().numpy()[0]
+    ref = -s / (12 * L * L)
+    ref[0] += 1.0
+    assert np.abs(w - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
