@@ -10,10 +10,18 @@
 // Accumulation is FP32 (v_mfma_f32_16x16x32_bf16); the result is stored as
 // interleaved FP32 complex and transformed back in FP64.
 //
-// The MFMA wants 8 consecutive k of one row per lane.  An operand whose
-// contracted index is contiguous in memory (left factor as is, right factor
-// conjugated) is copied to LDS with 16-byte moves; the other orientation is
-// transposed while staging (8 rows of one k per 16-byte load, scattered).
+// The MFMA wants 8 consecutive k of one row per lane.  Each operand tile is
+// copied to LDS with 16-byte moves in the orientation it has in memory:
+//  * contracted index contiguous (left factor as is, right factor
+//    conjugated): LDS [rows][k], one 16-byte read per fragment;
+//  * the other orientation: LDS [k][rows], read with the CDNA4 transposing
+//    LDS load (ds_read_b64_tr_b16), two per fragment.  Its rows are XOR-
+//    swizzled in 32-byte segments so that both the 16-byte stores and the
+//    transposing reads are free of bank conflicts.
+// A work-group computes a 64 x 64 tile of one mode with four wavefronts of
+// 2 x 2 blocks of 16 x 16; K is staged in chunks of 32.  The kernel is built
+// for three wavefronts per SIMD (the A fragments are read per block row to
+// stay within that register budget).
 #include "pm_common.h"
 #include "pm_kernels.h"
 
@@ -23,16 +31,21 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBM = 64, kBN = 64, kBK = 32;
-constexpr int kPadK = 8;                     // row pitch 40 elements = 80 B: conflict-free 16-B reads
-constexpr int kPitch = kBK + kPadK;
-constexpr int kThreadsB = 256;               // 4 wavefronts, 2 x 2, each 2 x 2 blocks of 16 x 16
-
-__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+constexpr int kBM = 64, kBK = 32;
+constexpr int kWaves = 4;
+constexpr int kThreadsB = kWave * kWaves;    // 2 x 2 wavefronts, each 2 x 2 blocks of 16 x 16
+constexpr int kPitchK = kBK + 8;             // [rows][k] tiles: 80-B rows, conflict-free 16-B reads
+constexpr int kPlaneElems = kBM * kPitchK;   // LDS region of one plane (>= kBK * kBM for [k][rows])
+constexpr int kTileElems = 4 * kPlaneElems;  // one operand tile, four planes
+constexpr int kVecs = 4 * (4 * kBM) / kThreadsB;   // 16-byte vectors staged per thread and operand
+static_assert(kVecs == 4, "one vector per plane and thread");
+static_assert(kBK * kBM <= kPlaneElems, "transposed tile must fit the plane region");
 
 __device__ __forceinline__ f4 mfma_bf16(uint4 a, uint4 b, f4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a), as_bf16x8(b), c, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                  c, 0, 0, 0);
 }
 
 // zero the bf16 elements e >= valid of an 8-element vector
@@ -41,8 +54,7 @@ __device__ __forceinline__ uint4 mask_tail(uint4 v, int valid) {
   uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
-    const int lo = 2 * d, hi = 2 * d + 1;
-    uint32_t keep = (lo < valid ? 0x0000ffffu : 0u) | (hi < valid ? 0xffff0000u : 0u);
+    const uint32_t keep = (2 * d < valid ? 0x0000ffffu : 0u) | (2 * d + 1 < valid ? 0xffff0000u : 0u);
     w[d] &= keep;
   }
   return make_uint4(w[0], w[1], w[2], w[3]);
@@ -52,70 +64,87 @@ __device__ __forceinline__ uint4 flip_sign(uint4 v) {
   return make_uint4(v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u, v.w ^ 0x80008000u);
 }
 
-struct Operand {
-  const uint16_t* base;   // mode base: 4 planes of n * ld elements
-  size_t plane;           // n * ld
-  int ld;
-  bool kcontig;           // contracted index contiguous in memory
-  bool conj;              // negate the imaginary planes
+// Segment swizzle of row k of a [k][64] tile: 16-element (32-byte) segment s
+// of row k is stored at segment s ^ seg_swizzle(k).  A transposing read
+// touches rows k = 8g + 4h + e (e = 0..3) of one segment; with 128-byte rows
+// the swizzle spreads the rows of one read over all 64 banks.
+__device__ __forceinline__ int seg_swizzle(int k) { return (k & 3) ^ ((k >> 3) & 1); }
+
+// One operand tile of 64 rows x 32 k.  KC: element (row, k) of the operand
+// sits at base[row * ld + k] (contracted index contiguous), else at
+// base[k * ld + row].  Rows and k beyond n read as zero (the padding columns
+// of a plane are never written, so k >= n is masked inside a vector too).
+template <bool KC>
+struct TileOp {
+  __device__ static __forceinline__ void load(const uint16_t* base, size_t plane, int ld, int n, int row0, int k0,
+                                              int tid, bool conj, uint4 (&r)[kVecs]) {
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) {
+      const uint16_t* pb = base + static_cast<size_t>(pl) * plane;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if constexpr (KC) {
+        const int row = tid >> 2, kc = tid & 3;   // 64 rows x 4 vectors of 8 k
+        const int gr = row0 + row, gk = k0 + 8 * kc;
+        if (gr < n && gk < n)
+          v = mask_tail(*reinterpret_cast<const uint4*>(pb + static_cast<size_t>(gr) * ld + gk), n - gk);
+      } else {
+        const int kk = tid >> 3, rc = tid & 7;    // 32 k x 8 vectors of 8 rows
+        const int gk = k0 + kk, gr = row0 + 8 * rc;
+        if (gk < n && gr < n)
+          v = mask_tail(*reinterpret_cast<const uint4*>(pb + static_cast<size_t>(gk) * ld + gr), n - gr);
+      }
+      if (conj && pl >= 2) v = flip_sign(v);
+      r[pl] = v;
+    }
+  }
+
+  __device__ static __forceinline__ void store(uint16_t* tile, int tid, const uint4 (&r)[kVecs]) {
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) {
+      uint16_t* p = tile + pl * kPlaneElems;
+      if constexpr (KC) {
+        const int row = tid >> 2, kc = tid & 3;
+        *reinterpret_cast<uint4*>(p + row * kPitchK + 8 * kc) = r[pl];
+      } else {
+        const int kk = tid >> 3, rc = tid & 7;
+        *reinterpret_cast<uint4*>(p + kk * kBM + (((rc >> 1) ^ seg_swizzle(kk)) << 4) + 8 * (rc & 1)) = r[pl];
+      }
+    }
+  }
+
+  // MFMA fragment of rows w0..w0+15 (w0 a multiple of 16): lane l receives
+  // row w0 + l % 16 and k = 8 (l / 16) .. 8 (l / 16) + 7.
+  __device__ static __forceinline__ uint4 frag(const uint16_t* p, int w0, int lane) {
+    if constexpr (KC) {
+      return *reinterpret_cast<const uint4*>(p + (w0 + (lane & 15)) * kPitchK + 8 * (lane >> 4));
+    } else {
+      // The transposing read hands lane 16g + j element j % 4 of the 8-byte
+      // words addressed by lanes 16g + j / 4 + 4t, t = 0..3, as its element
+      // t.  Lane 16g + 4e + c therefore addresses row k = 8g + 4h + e,
+      // columns w0 + 4c .. w0 + 4c + 3, and lane 16g + j receives column
+      // w0 + j at rows 8g + 4h + t.
+      const int g = lane >> 4, e = (lane >> 2) & 3, c = lane & 3;
+      uint2 half[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = 8 * g + 4 * h + e;
+        const uint16_t* a = p + k * kBM + (((w0 >> 4) ^ seg_swizzle(k)) << 4) + 4 * c;
+        const s4 v = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) s4*)(a));
+        half[h] = __builtin_bit_cast(uint2, v);
+      }
+      return make_uint4(half[0].x, half[0].y, half[1].x, half[1].y);
+    }
+  }
 };
 
-// Stage one 64 x 32 (rows x k) tile of an operand into registers.
-//   kcontig: element (row, k) at base[row * ld + k]  -> 16-B vector = 8 k of one row
-//   else   : element (row, k) at base[k * ld + row]  -> 16-B vector = 8 rows of one k
-__device__ __forceinline__ void load_tile(const Operand& op, int n, int row0, int k0, int tid, uint4 (&r)[4]) {
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int q = tid + kThreadsB * u;           // 0..1023
-    const int plane = q >> 8;                    // 4 planes x 256 vectors
-    const int w = q & 255;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    const uint16_t* pb = op.base + static_cast<size_t>(plane) * op.plane;
-    if (op.kcontig) {
-      const int row = w >> 2, kc = w & 3;        // 64 rows x 4 vectors of 8 k
-      const int gr = row0 + row, gk = k0 + 8 * kc;
-      if (gr < n && gk < n) {
-        v = *reinterpret_cast<const uint4*>(pb + static_cast<size_t>(gr) * op.ld + gk);
-        v = mask_tail(v, n - gk);
-      }
-    } else {
-      const int kk = w >> 3, rc = w & 7;         // 32 k x 8 vectors of 8 rows
-      const int gk = k0 + kk, gr = row0 + 8 * rc;
-      if (gk < n && gr < n) {
-        v = *reinterpret_cast<const uint4*>(pb + static_cast<size_t>(gk) * op.ld + gr);
-        v = mask_tail(v, n - gr);
-      }
-    }
-    if (op.conj && plane >= 2) v = flip_sign(v);
-    r[u] = v;
-  }
-}
-
-__device__ __forceinline__ void store_tile(const Operand& op, uint16_t (*lds)[kBM][kPitch], int tid,
-                                           const uint4 (&r)[4]) {
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int q = tid + kThreadsB * u;
-    const int plane = q >> 8;
-    const int w = q & 255;
-    if (op.kcontig) {
-      const int row = w >> 2, kc = w & 3;
-      *reinterpret_cast<uint4*>(&lds[plane][row][8 * kc]) = r[u];
-    } else {
-      const int kk = w >> 3, rc = w & 7;
-      const uint32_t d[4] = {r[u].x, r[u].y, r[u].z, r[u].w};
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const uint16_t h = static_cast<uint16_t>((e & 1) ? (d[e >> 1] >> 16) : (d[e >> 1] & 0xffffu));
-        lds[plane][8 * rc + e][kk] = h;
-      }
-    }
-  }
-}
-
-__global__ __launch_bounds__(kThreadsB) void k_cgemm_bf16x3(GemmArgs args) {
-  __shared__ uint16_t As[4][kBM][kPitch];
-  __shared__ uint16_t Bs[4][kBN][kPitch];
+template <bool OPA, bool OPB>
+__global__ __launch_bounds__(kThreadsB, 3) void k_cgemm_bf16x3(GemmArgs args) {
+  constexpr bool AKC = !OPA;   // left factor as is: rows contiguous in k
+  constexpr bool BKC = OPB;    // right factor conjugated: (Y^+)[k][j] = conj(Y[j][k])
+  using TA = TileOp<AKC>;
+  using TB = TileOp<BKC>;
+  __shared__ __align__(16) uint16_t As[kTileElems];
+  __shared__ __align__(16) uint16_t Bs[kTileElems];
 
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   int jidx = 0;
@@ -131,23 +160,13 @@ __global__ __launch_bounds__(kThreadsB) void k_cgemm_bf16x3(GemmArgs args) {
   const int n = jb.n, L = jb.L;
   const int ld = bf16_ld(n);
   const size_t plane = static_cast<size_t>(n) * ld;
-  const int pa = jb.opA ? (L - p) % L : p;
-  const int pb = jb.opB ? (L - p) % L : p;
-
-  Operand oa, ob;
-  oa.base = reinterpret_cast<const uint16_t*>(jb.A) + static_cast<size_t>(pa) * 4 * plane;
-  oa.plane = plane;
-  oa.ld = ld;
-  oa.kcontig = jb.opA == 0;      // left factor as is: [i][k] rows contiguous in k
-  oa.conj = jb.opA != 0;
-  ob.base = reinterpret_cast<const uint16_t*>(jb.B) + static_cast<size_t>(pb) * 4 * plane;
-  ob.plane = plane;
-  ob.ld = ld;
-  ob.kcontig = jb.opB != 0;      // right factor conjugated: (Y^+)[k][j] = conj(Y[j][k])
-  ob.conj = jb.opB != 0;
+  const int pa = OPA ? (L - p) % L : p;
+  const int pb = OPB ? (L - p) % L : p;
+  const uint16_t* Ab = reinterpret_cast<const uint16_t*>(jb.A) + static_cast<size_t>(pa) * 4 * plane;
+  const uint16_t* Bb = reinterpret_cast<const uint16_t*>(jb.B) + static_cast<size_t>(pb) * 4 * plane;
   float2* __restrict__ Cg = reinterpret_cast<float2*>(jb.C) + static_cast<size_t>(p) * n * n;
 
-  const int row0 = tm * kBM, col0 = tn * kBN;
+  const int row0 = tm * kBM, col0 = tn * kBM;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
@@ -165,48 +184,45 @@ __global__ __launch_bounds__(kThreadsB) void k_cgemm_bf16x3(GemmArgs args) {
 #pragma unroll
   for (int b = 0; b < 2; ++b) nact[b] = col0 + wcol0 + 16 * b < n;
 
-  uint4 ra[4], rb[4];
+  uint4 ra[kVecs], rb[kVecs];
   const int nk = (n + kBK - 1) / kBK;
-  load_tile(oa, n, row0, 0, tid, ra);
-  load_tile(ob, n, col0, 0, tid, rb);
+  TA::load(Ab, plane, ld, n, row0, 0, tid, OPA, ra);
+  TB::load(Bb, plane, ld, n, col0, 0, tid, OPB, rb);
   for (int c = 0; c < nk; ++c) {
-    store_tile(oa, As, tid, ra);
-    store_tile(ob, Bs, tid, rb);
+    TA::store(As, tid, ra);
+    TB::store(Bs, tid, rb);
     __syncthreads();
     if (c + 1 < nk) {
-      load_tile(oa, n, row0, (c + 1) * kBK, tid, ra);
-      load_tile(ob, n, col0, (c + 1) * kBK, tid, rb);
+      TA::load(Ab, plane, ld, n, row0, (c + 1) * kBK, tid, OPA, ra);
+      TB::load(Bb, plane, ld, n, col0, (c + 1) * kBK, tid, OPB, rb);
     }
-    uint4 fa[2][4], fb[2][4];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int pl = 0; pl < 4; ++pl)
-        fa[a][pl] = *reinterpret_cast<const uint4*>(&As[pl][wrow0 + 16 * a + li][8 * lk]);
+    uint4 fb[2][4];
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int pl = 0; pl < 4; ++pl)
-        fb[b][pl] = *reinterpret_cast<const uint4*>(&Bs[pl][wcol0 + 16 * b + li][8 * lk]);
+      for (int pl = 0; pl < 4; ++pl) fb[b][pl] = TB::frag(Bs + pl * kPlaneElems, wcol0 + 16 * b, lane);
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      const uint4 nih = flip_sign(fa[a][2]), nil = flip_sign(fa[a][3]);
+      uint4 fa[4];
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) fa[pl] = TA::frag(As + pl * kPlaneElems, wrow0 + 16 * a, lane);
+      const uint4 nih = flip_sign(fa[2]), nil = flip_sign(fa[3]);
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         if (mact[a] && nact[b]) {
           // Re: Xr Yr - Xi Yi
-          cr[a][b] = mfma_bf16(fa[a][0], fb[b][0], cr[a][b]);
-          ci[a][b] = mfma_bf16(fa[a][0], fb[b][2], ci[a][b]);
-          cr[a][b] = mfma_bf16(fa[a][0], fb[b][1], cr[a][b]);
-          ci[a][b] = mfma_bf16(fa[a][0], fb[b][3], ci[a][b]);
-          cr[a][b] = mfma_bf16(fa[a][1], fb[b][0], cr[a][b]);
-          ci[a][b] = mfma_bf16(fa[a][1], fb[b][2], ci[a][b]);
+          cr[a][b] = mfma_bf16(fa[0], fb[b][0], cr[a][b]);
+          ci[a][b] = mfma_bf16(fa[0], fb[b][2], ci[a][b]);
+          cr[a][b] = mfma_bf16(fa[0], fb[b][1], cr[a][b]);
+          ci[a][b] = mfma_bf16(fa[0], fb[b][3], ci[a][b]);
+          cr[a][b] = mfma_bf16(fa[1], fb[b][0], cr[a][b]);
+          ci[a][b] = mfma_bf16(fa[1], fb[b][2], ci[a][b]);
           cr[a][b] = mfma_bf16(nih, fb[b][2], cr[a][b]);
-          ci[a][b] = mfma_bf16(fa[a][2], fb[b][0], ci[a][b]);
+          ci[a][b] = mfma_bf16(fa[2], fb[b][0], ci[a][b]);
           cr[a][b] = mfma_bf16(nih, fb[b][3], cr[a][b]);
-          ci[a][b] = mfma_bf16(fa[a][2], fb[b][1], ci[a][b]);
+          ci[a][b] = mfma_bf16(fa[2], fb[b][1], ci[a][b]);
           cr[a][b] = mfma_bf16(nil, fb[b][2], cr[a][b]);
-          ci[a][b] = mfma_bf16(fa[a][3], fb[b][0], ci[a][b]);
+          ci[a][b] = mfma_bf16(fa[3], fb[b][0], ci[a][b]);
         }
       }
     }
@@ -233,7 +249,12 @@ int gemm_tile_bf16() { return kBM; }
 
 hipError_t launch_gemm_bf16(const GemmArgs& a, hipStream_t s) {
   if (a.njobs <= 0 || a.total_tiles <= 0) return hipSuccess;
-  k_cgemm_bf16x3<<<a.total_tiles, kThreadsB, 0, s>>>(a);
+  const int oa = a.jobs[0].opA, ob = a.jobs[0].opB;   // shared by all jobs of a launch
+  const int g = a.total_tiles;
+  if (!oa && !ob) k_cgemm_bf16x3<false, false><<<g, kThreadsB, 0, s>>>(a);
+  else if (!oa && ob) k_cgemm_bf16x3<false, true><<<g, kThreadsB, 0, s>>>(a);
+  else if (oa && !ob) k_cgemm_bf16x3<true, false><<<g, kThreadsB, 0, s>>>(a);
+  else k_cgemm_bf16x3<true, true><<<g, kThreadsB, 0, s>>>(a);
   return hipGetLastError();
 }
 
