@@ -51,12 +51,12 @@ __device__ __forceinline__ void split_bf16(double x, uint16_t& hi, uint16_t& lo)
   lo = bf16_rne(static_cast<float>(r));
 }
 
-// BF16 split layout of one mode: four planes (re_hi, re_lo, im_hi, im_lo),
-// each row-major [n][ld] with ld = n rounded up to a multiple of 8, so that a
-// lane of the product kernel can fetch 8 consecutive entries of a row with a
-// single 16-byte load.  The padding columns are never written (the product
-// kernel masks them).
-__device__ __forceinline__ size_t bf16_plane_elems(int n) { return static_cast<size_t>(bf16_ld(n)) * n; }
+// BF16 split layout: per mode a row-major [n][ld] array of 8-byte entries
+// (re_hi, re_lo, im_hi, im_lo as four BF16), ld = n rounded up to a multiple
+// of 8, so that 8 consecutive entries of a row start on a 64-byte boundary
+// and one lane of the transforms stores one entry with one 8-byte write.  The
+// padding columns are never written (the product kernel masks them).
+__device__ __forceinline__ size_t bf16_mode_entries(int n) { return static_cast<size_t>(bf16_ld(n)) * n; }
 
 // Store mode p of entry e (matrix size n, E = n*n entries per mode).
 template <FourierType FT>
@@ -68,16 +68,12 @@ __device__ __forceinline__ void store_mode(void* dst, int E, int n, int p, int e
         make_float2(static_cast<float>(v.x), static_cast<float>(v.y));
   } else {
     const int i = e / n, j = e - (e / n) * n;
-    const size_t plane = bf16_plane_elems(n);
-    uint16_t* base = reinterpret_cast<uint16_t*>(dst) + static_cast<size_t>(p) * 4 * plane;
-    const size_t off = static_cast<size_t>(i) * bf16_ld(n) + j;
     uint16_t rh, rl, ih, il;
     split_bf16(v.x, rh, rl);
     split_bf16(v.y, ih, il);
-    base[off] = rh;
-    base[plane + off] = rl;
-    base[2 * plane + off] = ih;
-    base[3 * plane + off] = il;
+    const size_t off = static_cast<size_t>(p) * bf16_mode_entries(n) + static_cast<size_t>(i) * bf16_ld(n) + j;
+    reinterpret_cast<uint2*>(dst)[off] =
+        make_uint2(rh | (static_cast<uint32_t>(rl) << 16), ih | (static_cast<uint32_t>(il) << 16));
   }
 }
 

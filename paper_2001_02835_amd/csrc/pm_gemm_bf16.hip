@@ -1,17 +1,19 @@
 // Mode-wise complex products in split-BF16 form (FFT-CONV Step 3, eq. (8)).
 //
 // Each Fourier coefficient x (an FP64 value from the forward transform) was
-// stored as x = hi + lo with hi = RNE_bf16(x) and lo = RNE_bf16(x - hi), in
-// four BF16 planes per mode: re_hi, re_lo, im_hi, im_lo, each row-major
-// [N][ld] with ld = N rounded up to 8.  A real product X Y is then
+// stored as x = hi + lo with hi = RNE_bf16(x) and lo = RNE_bf16(x - hi), as
+// one 8-byte entry (re_hi, re_lo, im_hi, im_lo) of a row-major [N][ld] array
+// per mode, ld = N rounded up to 8.  A real product X Y is then
 // approximated by hi_X hi_Y + hi_X lo_Y + lo_X hi_Y (the lo*lo term is below
 // the FP32 accumulation error), and a complex product by four real ones:
 //   Re = Xr Yr - Xi Yi,  Im = Xr Yi + Xi Yr   -> 12 BF16 MFMAs per block.
 // Accumulation is FP32 (v_mfma_f32_16x16x32_bf16); the result is stored as
 // interleaved FP32 complex and transformed back in FP64.
 //
-// The MFMA wants 8 consecutive k of one row per lane.  Each operand tile is
-// copied to LDS with 16-byte moves in the orientation it has in memory:
+// The MFMA wants 8 consecutive k of one row per lane.  A thread fetches 8
+// consecutive entries (64 bytes) and separates them into four planes of 8
+// BF16 values, which go to LDS with 16-byte stores in the orientation the
+// operand has in memory:
 //  * contracted index contiguous (left factor as is, right factor
 //    conjugated): LDS [rows][k], one 16-byte read per fragment;
 //  * the other orientation: LDS [k][rows], read with the CDNA4 transposing
@@ -70,31 +72,59 @@ __device__ __forceinline__ uint4 flip_sign(uint4 v) {
 // the swizzle spreads the rows of one read over all 64 banks.
 __device__ __forceinline__ int seg_swizzle(int k) { return (k & 3) ^ ((k >> 3) & 1); }
 
+// Split 8 consecutive entries q (two per 16-byte vector) into the four
+// planes: dword t of plane P holds component P of entries 2t and 2t + 1.
+__device__ __forceinline__ void split_planes(const uint4 (&q)[4], uint4 (&pl)[4]) {
+  uint32_t w[4][4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    w[0][t] = (q[t].x & 0xffffu) | (q[t].z << 16);
+    w[1][t] = (q[t].x >> 16) | (q[t].z & 0xffff0000u);
+    w[2][t] = (q[t].y & 0xffffu) | (q[t].w << 16);
+    w[3][t] = (q[t].y >> 16) | (q[t].w & 0xffff0000u);
+  }
+#pragma unroll
+  for (int P = 0; P < 4; ++P) pl[P] = make_uint4(w[P][0], w[P][1], w[P][2], w[P][3]);
+}
+
 // One operand tile of 64 rows x 32 k.  KC: element (row, k) of the operand
-// sits at base[row * ld + k] (contracted index contiguous), else at
+// is entry base[row * ld + k] (contracted index contiguous), else entry
 // base[k * ld + row].  Rows and k beyond n read as zero (the padding columns
-// of a plane are never written, so k >= n is masked inside a vector too).
+// are never written, so k >= n is masked inside a vector too).
 template <bool KC>
 struct TileOp {
-  __device__ static __forceinline__ void load(const uint16_t* base, size_t plane, int ld, int n, int row0, int k0,
-                                              int tid, bool conj, uint4 (&r)[kVecs]) {
+  __device__ static __forceinline__ void load(const uint2* base, int ld, int n, int row0, int k0, int tid,
+                                              bool conj, uint4 (&r)[kVecs]) {
+    int gr, gk, valid;
+    size_t off;
+    if constexpr (KC) {
+      const int row = tid >> 2, kc = tid & 3;     // 64 rows x 4 runs of 8 k
+      gr = row0 + row;
+      gk = k0 + 8 * kc;
+      off = static_cast<size_t>(gr) * ld + gk;
+      valid = n - gk;
+    } else {
+      const int kk = tid >> 3, rc = tid & 7;      // 32 k x 8 runs of 8 rows
+      gk = k0 + kk;
+      gr = row0 + 8 * rc;
+      off = static_cast<size_t>(gk) * ld + gr;
+      valid = n - gr;
+    }
+    if (gr < n && gk < n) {
+      const uint4* src = reinterpret_cast<const uint4*>(base + off);
+      uint4 q[4];
 #pragma unroll
-    for (int pl = 0; pl < 4; ++pl) {
-      const uint16_t* pb = base + static_cast<size_t>(pl) * plane;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if constexpr (KC) {
-        const int row = tid >> 2, kc = tid & 3;   // 64 rows x 4 vectors of 8 k
-        const int gr = row0 + row, gk = k0 + 8 * kc;
-        if (gr < n && gk < n)
-          v = mask_tail(*reinterpret_cast<const uint4*>(pb + static_cast<size_t>(gr) * ld + gk), n - gk);
-      } else {
-        const int kk = tid >> 3, rc = tid & 7;    // 32 k x 8 vectors of 8 rows
-        const int gk = k0 + kk, gr = row0 + 8 * rc;
-        if (gk < n && gr < n)
-          v = mask_tail(*reinterpret_cast<const uint4*>(pb + static_cast<size_t>(gk) * ld + gr), n - gr);
+      for (int t = 0; t < 4; ++t) q[t] = src[t];
+      split_planes(q, r);
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) r[pl] = mask_tail(r[pl], valid);
+      if (conj) {
+        r[2] = flip_sign(r[2]);
+        r[3] = flip_sign(r[3]);
       }
-      if (conj && pl >= 2) v = flip_sign(v);
-      r[pl] = v;
+    } else {
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) r[pl] = make_uint4(0, 0, 0, 0);
     }
   }
 
@@ -159,11 +189,11 @@ __global__ __launch_bounds__(kThreadsB, 3) void k_cgemm_bf16x3(GemmArgs args) {
   const int tn = rem - tm * jb.tiles_n;
   const int n = jb.n, L = jb.L;
   const int ld = bf16_ld(n);
-  const size_t plane = static_cast<size_t>(n) * ld;
+  const size_t mode = static_cast<size_t>(n) * ld;
   const int pa = OPA ? (L - p) % L : p;
   const int pb = OPB ? (L - p) % L : p;
-  const uint16_t* Ab = reinterpret_cast<const uint16_t*>(jb.A) + static_cast<size_t>(pa) * 4 * plane;
-  const uint16_t* Bb = reinterpret_cast<const uint16_t*>(jb.B) + static_cast<size_t>(pb) * 4 * plane;
+  const uint2* Ab = reinterpret_cast<const uint2*>(jb.A) + static_cast<size_t>(pa) * mode;
+  const uint2* Bb = reinterpret_cast<const uint2*>(jb.B) + static_cast<size_t>(pb) * mode;
   float2* __restrict__ Cg = reinterpret_cast<float2*>(jb.C) + static_cast<size_t>(p) * n * n;
 
   const int row0 = tm * kBM, col0 = tn * kBM;
@@ -186,15 +216,15 @@ __global__ __launch_bounds__(kThreadsB, 3) void k_cgemm_bf16x3(GemmArgs args) {
 
   uint4 ra[kVecs], rb[kVecs];
   const int nk = (n + kBK - 1) / kBK;
-  TA::load(Ab, plane, ld, n, row0, 0, tid, OPA, ra);
-  TB::load(Bb, plane, ld, n, col0, 0, tid, OPB, rb);
+  TA::load(Ab, ld, n, row0, 0, tid, OPA, ra);
+  TB::load(Bb, ld, n, col0, 0, tid, OPB, rb);
   for (int c = 0; c < nk; ++c) {
     TA::store(As, tid, ra);
     TB::store(Bs, tid, rb);
     __syncthreads();
     if (c + 1 < nk) {
-      TA::load(Ab, plane, ld, n, row0, (c + 1) * kBK, tid, OPA, ra);
-      TB::load(Bb, plane, ld, n, col0, (c + 1) * kBK, tid, OPB, rb);
+      TA::load(Ab, ld, n, row0, (c + 1) * kBK, tid, OPA, ra);
+      TB::load(Bb, ld, n, col0, (c + 1) * kBK, tid, OPB, rb);
     }
     uint4 fb[2][4];
 #pragma unroll

@@ -51,7 +51,7 @@ size_t operand_bytes(int n, int L, int prec) {
   switch (prec) {
     case PM_PREC_FP64: return E * L * 16;
     case PM_PREC_FP32: return E * L * 8;
-    default: return static_cast<size_t>(bf16_ld(n)) * n * 4 * 2 * L;   // four BF16 planes
+    default: return static_cast<size_t>(bf16_ld(n)) * n * 8 * L;   // 8-byte split entries, rows padded to ld
   }
 }
 // Bytes of the product coefficients over L modes (FP64 or FP32 complex).
