@@ -13,7 +13,9 @@ Readings of the paper used here (Section 2, eqs. (2)-(3)):
 * the order-0 drift is dropped (X^(0) = 0): the expansion is around the
   classical vacuum, where the force vanishes;
 * all four directions are updated from the same old links (Jacobi order);
-* no stochastic gauge fixing (the paper omits its details).
+* the Langevin and MD steps carry no gauge fixing (the paper omits its
+  details); ``gauge_fix`` below is a separate step of this
+  implementation's own design.
 """
 from __future__ import annotations
 
@@ -187,3 +189,62 @@ def _series_power(x: np.ndarray, p: int) -> np.ndarray:
     for _ in range(p - 1):
         out = ser.star(out, x)
     return out
+
+
+# --------------------------------------------------------------------------
+# Stochastic gauge fixing (the paper states that it is used and omits its
+# details, Section 2; the form below is this implementation's design).
+#
+# The reduced model is invariant under U_mu -> Omega U_mu Omega^+ with one
+# Omega in SU(N) for all directions.  Writing U_mu = V_mu Gamma_mu with the
+# twist eaters Gamma_mu = U_mu^(0), this acts on the fluctuation as
+# V_mu -> Omega V_mu (Gamma_mu Omega^+ Gamma_mu^+): conjugation by Gamma_mu
+# plays the part of the lattice shift by mu, and the reduced-model Landau
+# gauge maximises F(Omega) = sum_mu Re Tr (Omega U_mu Omega^+ Gamma_mu^+).
+# Its gradient at Omega = 1 is carried by
+#     G = sum_mu ( U_mu Gamma_mu^+ - Gamma_mu^+ U_mu ),
+# and one steepest-ascent step of size alpha is Omega = exp(Y) with
+#     Y = -(alpha/2) [ (G - G^+) - Tr(G - G^+)/N ]
+# (anti-Hermitian, traceless).  G^(0) = 0, so Omega^(0) = 1 and the vacuum
+# is left alone.  To first order a pure-gauge fluctuation
+# U_mu^(1) = i [w, Gamma_mu] with Gamma_nu w Gamma_nu^+ = phi_nu w for all
+# nu is damped by the factor 1 - alpha lambda, lambda = sum_nu |1 - phi_nu|^2
+# (the lattice Laplacian of that mode).
+# --------------------------------------------------------------------------
+
+
+def gauge_generator(u: np.ndarray) -> np.ndarray:
+    """G = sum_mu (U_mu * Gamma_mu^+ - Gamma_mu^+ * U_mu), Gamma_mu = U_mu^(0)
+    taken as an order-0 series; every * the truncated star product."""
+    g = np.zeros_like(u[0])
+    for mu in range(4):
+        v = np.zeros_like(u[mu])
+        v[0] = u[mu, 0]
+        vd = ser.dagger(v)
+        g += ser.star(u[mu], vd) - ser.star(vd, u[mu])
+    return g
+
+
+def gauge_exponent(u: np.ndarray, alpha: float) -> np.ndarray:
+    """Y = -(alpha/2) [ (G - G^+) - Tr(G - G^+)/N ] for every order, Y^(0) = 0."""
+    g = gauge_generator(u)
+    n = u.shape[-1]
+    d = g - ser.dagger(g)
+    tr = np.trace(d, axis1=-2, axis2=-1)
+    y = -0.5 * alpha * (d - tr[:, None, None] / n * np.eye(n)[None])
+    y[0] = 0.0
+    return y
+
+
+def gauge_fix(u: np.ndarray, alpha: float) -> np.ndarray:
+    """One gauge-fixing step of one replica: U_mu <- Omega * U_mu * Omega^+
+    for every mu with the same Omega = exp(Y) (series exponential)."""
+    u = np.asarray(u, dtype=np.complex128)
+    om = ser.series_exp(gauge_exponent(u, alpha))
+    omd = ser.dagger(om)
+    return np.stack([ser.star(ser.star(om, u[mu]), omd) for mu in range(4)])
+
+
+def gauge_fix_replicas(u: np.ndarray, alpha: float) -> np.ndarray:
+    """Replica batch: u [R, 4, ntrunc+1, N, N]."""
+    return np.stack([gauge_fix(u[r], alpha) for r in range(u.shape[0])])
