@@ -284,6 +284,34 @@ pm_status nspt_md_trajectory(void* U, void* P, const void* eta, int replicas,
                              void* stream);
 
 /*
+ * nspt_gauge_fix - one stochastic gauge-fixing step for `replicas` link sets.
+ * The paper uses stochastic gauge fixing in its NSPT runs and omits the
+ * details (Section 2); the form here is this library's design.  The reduced
+ * model is invariant under U_mu -> Omega U_mu Omega^+ (one Omega for all
+ * directions).  With Gamma_mu = U_mu^(0) (the twist eaters) and every
+ * product the truncated star product:
+ *   G     = sum_mu ( U_mu * Gamma_mu^+ - Gamma_mu^+ * U_mu )
+ *   Y^(k) = -(alpha/2) [ D^(k) - Tr(D^(k))/N ],  D = G - G^+,  Y^(0) = 0
+ *   U_mu <- Omega * U_mu * Omega^+,  Omega = exp(Y),  for every mu.
+ * This is one steepest-ascent step of size alpha of the reduced-model Landau
+ * functional sum_mu Re Tr(Omega U_mu Omega^+ Gamma_mu^+).  To first order a
+ * pure-gauge fluctuation that is an eigenmode of the conjugations by the
+ * twist eaters, with phases phi_nu, is multiplied by
+ * 1 - alpha sum_nu |1 - phi_nu|^2; every mode is damped for 0 < alpha < 1/8.
+ * Gauge-invariant observables (nspt_action, nspt_wilson_loop) are unchanged
+ * up to rounding, and order 0 is left unchanged.
+ *   U      device complex128 [replicas][4][ntrunc+1][n][n], updated in place.
+ *   alpha  step size, finite and >= 0 (0 returns at once: Omega = 1).
+ * params is checked as for nspt_langevin_step (eps > 0), but eps is not
+ * used.  precision applies to the products.  The
+ * workspace is the one of nspt_langevin_step (nspt_workspace_size); U and
+ * the workspace must not overlap (PM_ERR_INVALID).
+ */
+pm_status nspt_gauge_fix(void* U, int replicas, const nspt_params* params, double alpha,
+                         int precision, void* workspace, size_t workspace_bytes,
+                         void* stream);
+
+/*
  * nspt_action - the action of eq. (1) at beta = 1 as a series in g, for
  * `replicas` link sets (the observable of the plaquette, i.e. the 1x1
  * Wilson loop: W^(k) = delta_k0 - S^(k) / (12 N)):

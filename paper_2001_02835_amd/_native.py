@@ -62,6 +62,7 @@ SIGNATURES = {
     "nspt_action": (_I, [_VP, _I, ctypes.POINTER(NsptParams), _I, _VP, _VP, _SZ, _VP]),
     "nspt_wilson_loop": (_I, [_VP, _I, ctypes.POINTER(NsptParams), _I, _I, _I, _VP, _VP, _SZ, _VP]),
     "nspt_md_trajectory": (_I, [_VP, _VP, _VP, _I, ctypes.POINTER(NsptParams), _I, _I, _VP, _SZ, _VP]),
+    "nspt_gauge_fix": (_I, [_VP, _I, ctypes.POINTER(NsptParams), _D, _I, _VP, _SZ, _VP]),
 }
 
 _lib = None

@@ -207,6 +207,23 @@ def nspt_md_trajectory(U: torch.Tensor, P: torch.Tensor, params: nat.NsptParams,
     return U, P
 
 
+def nspt_gauge_fix(U: torch.Tensor, params: nat.NsptParams, alpha: float, precision="fp64",
+                   ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """One stochastic gauge-fixing step of step size alpha on U [R, 4, ntrunc+1, n, n], in place."""
+    _series_check(U, "U")
+    R = U.shape[0]
+    p = _prec(precision)
+    need = nat.lib().nspt_workspace_size(R, ctypes.byref(params), p)
+    if need == 0:
+        raise ValueError("invalid NSPT parameters")
+    if ws is None:
+        ws = workspace(need, U.device)
+    st = nat.lib().nspt_gauge_fix(U.data_ptr(), R, ctypes.byref(params), float(alpha), p, ws.data_ptr(),
+                                  ws.numel(), _stream_ptr(U.device))
+    nat.check(st, "nspt_gauge_fix")
+    return U
+
+
 def nspt_action(U: torch.Tensor, params: nat.NsptParams, precision="fp64",
                 ws: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Action series S^(k) (float64 [R, ntrunc+1]) of link series U [R, 4, ntrunc+1, n, n]."""

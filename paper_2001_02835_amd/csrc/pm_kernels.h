@@ -61,8 +61,8 @@ struct ScaleJob {
   int nord;
   int L;
   double fixed_s;          // > 0: use it; 0: choose from the norms
-  int nser;
-  int pad_;
+  int nser;                // series stacked in partA (and in partB when nser_b == 0)
+  int nser_b;              // > 0: series stacked in partB
 };
 struct ScaleArgs { ScaleJob jobs[kMaxTransformJobs]; int njobs; };
 

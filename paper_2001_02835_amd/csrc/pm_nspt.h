@@ -15,6 +15,8 @@ pm_status nspt_series_action(const void* U, int replicas, const nspt_params* par
                              void* workspace, size_t workspace_bytes, hipStream_t stream);
 pm_status nspt_wilson(const void* U, int replicas, const nspt_params* params, int a, int b, int precision,
                       double* W, void* workspace, size_t workspace_bytes, hipStream_t stream);
+pm_status nspt_gauge(void* U, int replicas, const nspt_params* params, double alpha, int precision,
+                     void* workspace, size_t workspace_bytes, hipStream_t stream);
 pm_status nspt_md(void* U, void* P, const void* eta, int replicas, const nspt_params* params, int nsteps,
                   int precision, void* workspace, size_t workspace_bytes, hipStream_t stream);
 

@@ -236,6 +236,11 @@ struct Run {
   double2* trc;
   size_t series_elems;
   int qslot[4][4], pair[4][4];
+  // exponent series per replica: 4 (one per direction, Langevin and MD) or 1
+  // (gauge fixing: one Omega for all directions); with conj_update the update
+  // is U_m <- E U_m E^+ instead of U_m <- E_m U_m
+  int nexp = 4;
+  bool conj_update = false;
 
   Run(void* U, int R_, const nspt_params* p_, int prec_, void* workspace, hipStream_t s_)
       : l(layout(R_, p_, prec_)), p(p_), R(R_), prec(prec_), fin(in_type(prec_)), fout(out_type(prec_)), s(s_) {
@@ -624,8 +629,114 @@ struct Run {
     return st(timed(PM_PHASE_OTHER, s, [&] { return launch_force(fa, n, nord, s); }));
   }
 
+  // ---- gauge-fixing exponent (after links_forward): with V_m = U_m^(0),
+  //      G = sum_m (U_m V_m^+ - V_m^+ U_m) and
+  //      Y = -(alpha/2) [(G - G^+) - Tr(G - G^+)/N] into Ypt(r, 0, 1), one per replica
+  pm_status gauge_exponent(double alpha) {
+    const int n = l.n, E = l.E, nord = l.nord, L = l.L;
+    // V_m: the order-0 coefficient alone, i.e. the same matrix at every mode
+    {
+      FwdArgs fw{};
+      auto flush = [&]() -> pm_status {
+        pm_status e = st(timed(PM_PHASE_FORWARD, s, [&] { return launch_forward(fw, L, E, fin, s); }));
+        fw.njobs = 0;
+        return e;
+      };
+      for (int r = 0; r < R; ++r)
+        for (int m = 0; m < 4; ++m) {
+          if (fw.njobs == kMaxTransformJobs) { pm_status e = flush(); if (e) return e; }
+          FwdJob& j = fw.jobs[fw.njobs++];
+          j.src = Useries(r, m);
+          j.dst = Xt(r, m);
+          j.rec = rec;
+          j.E = E;
+          j.nord = 1;
+          j.n = n;
+        }
+      pm_status e = flush();
+      if (e) return e;
+    }
+    {
+      GemmBatch nc{fin, s, 1}, cn{fin, s, 2};
+      for (int r = 0; r < R; ++r)
+        for (int m = 0; m < 4; ++m) {
+          nc.add(Ut(r, m), Xt(r, m), G(r, m), n, L);        // U_m V_m^+
+          cn.add(Xt(r, m), Ut(r, m), G(r, 4 + m), n, L);    // V_m^+ U_m
+        }
+      nc.flush();
+      cn.flush();
+      if (nc.status || cn.status) return PM_ERR_DEVICE;
+    }
+    // G in the (unscaled) time domain
+    {
+      CombineArgs ca{};
+      auto flush = [&]() -> pm_status {
+        if (ca.njobs == 0) return PM_OK;
+        pm_status e = st(timed(PM_PHASE_INVERSE, s, [&] { return launch_inv_combine(ca, L, E, fout, s); }));
+        ca.njobs = 0;
+        return e;
+      };
+      for (int r = 0; r < R; ++r) {
+        if (ca.njobs == kMaxCombineJobs) { pm_status e = flush(); if (e) return e; }
+        CombineJob& j = ca.jobs[ca.njobs++];
+        j.nsrc = 8;
+        for (int m = 0; m < 4; ++m) {
+          j.src[m] = G(r, m);
+          j.coef[m] = make_double2(1.0, 0.0);
+          j.src[4 + m] = G(r, 4 + m);
+          j.coef[4 + m] = make_double2(-1.0, 0.0);
+        }
+        j.dst = Mser(r, 0);
+        j.rec = rec;
+        j.E = E;
+        j.nord = nord;
+        j.kmin = 0;
+      }
+      pm_status e = flush();
+      if (e) return e;
+    }
+    TraceArgs ta{};
+    for (int r = 0; r < R; ++r) {
+      if (ta.njobs == kMaxTransformJobs) {
+        pm_status e = st(timed(PM_PHASE_OTHER, s, [&] { return launch_trace(ta, nord, s); }));
+        if (e) return e;
+        ta.njobs = 0;
+      }
+      TraceJob& j = ta.jobs[ta.njobs++];
+      j.src = Mser(r, 0);
+      j.out = trc + static_cast<size_t>(r) * 4 * nord;
+      j.n = n;
+      j.nord = nord;
+    }
+    pm_status e = st(timed(PM_PHASE_OTHER, s, [&] { return launch_trace(ta, nord, s); }));
+    if (e) return e;
+    // Y = -eps (D - Tr D / N), D = G - G^+, with eps = alpha / 2 and no noise
+    ForceArgs fa{};
+    fa.md = 0;
+    fa.eps = 0.5 * alpha;
+    fa.noise_amp = 0.0;
+    for (int r = 0; r < R; ++r) {
+      if (fa.njobs == kMaxForceJobs) {
+        e = st(timed(PM_PHASE_OTHER, s, [&] { return launch_force(fa, n, nord, s); }));
+        if (e) return e;
+        fa.njobs = 0;
+      }
+      ForceJob& j = fa.jobs[fa.njobs++];
+      j.M = Mser(r, 0);
+      j.tr = trc + static_cast<size_t>(r) * 4 * nord;
+      j.eta = nullptr;
+      j.P = nullptr;
+      j.Y = Ypt(r, 0, 1);
+      j.rec = unit;
+      j.n = n;
+      j.nord = nord;
+    }
+    return st(timed(PM_PHASE_OTHER, s, [&] { return launch_force(fa, n, nord, s); }));
+  }
+
   // ---- exponential of Y (Y^1 in Ypt(.,.,1), scaled) into Zf, then the link
-  //      update U_m <- E_m * U_m (orders >= 1)
+  //      update U_m <- E_m * U_m (orders >= 1); nexp == 1: one exponent per
+  //      replica for all m; conj_update: U_m <- E * U_m * E^+
   pm_status exp_and_update() {
     const int n = l.n, E = l.E, nord = l.nord, L = l.L, b = l.b;
     // s' from the norms of Y (all replicas and directions) against those of
@@ -638,11 +749,11 @@ struct Run {
         return e;
       };
       for (int r = 0; r < R; ++r)
-        for (int mu = 0; mu < 4; ++mu) {
+        for (int mu = 0; mu < nexp; ++mu) {
           if (na.njobs == kMaxTransformJobs) { pm_status e = flush(); if (e) return e; }
           NormJob& j = na.jobs[na.njobs++];
           j.src = Ypt(r, mu, 1);
-          j.partial = partY + (static_cast<size_t>(r) * 4 + mu) * nord * kNormChunks;
+          j.partial = partY + (static_cast<size_t>(r) * nexp + mu) * nord * kNormChunks;
           j.E = E;
           j.nord = nord;
         }
@@ -656,7 +767,8 @@ struct Run {
       sa.jobs[0].nord = nord;
       sa.jobs[0].L = L;
       sa.jobs[0].fixed_s = 0.0;
-      sa.jobs[0].nser = 4 * R;
+      sa.jobs[0].nser = nexp * R;
+      sa.jobs[0].nser_b = 4 * R;
       e = st(timed(PM_PHASE_RESCALE, s, [&] { return launch_scale(sa, s); }));
       if (e) return e;
       SeriesScaleArgs ss{};
@@ -666,7 +778,7 @@ struct Run {
         return e2;
       };
       for (int r = 0; r < R; ++r)
-        for (int mu = 0; mu < 4; ++mu) {
+        for (int mu = 0; mu < nexp; ++mu) {
           if (ss.njobs == kMaxSeriesScaleJobs) { e = flush2(); if (e) return e; }
           SeriesScaleJob& j = ss.jobs[ss.njobs++];
           j.x = Ypt(r, mu, 1);
@@ -681,7 +793,7 @@ struct Run {
     {
       FwdArgs fw{};
       for (int r = 0; r < R; ++r)
-        for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < nexp; ++m) {
           if (fw.njobs == kMaxTransformJobs) {
             pm_status e = st(timed(PM_PHASE_FORWARD, s, [&] { return launch_forward(fw, L, E, fin, s); }));
             if (e) return e;
@@ -702,14 +814,14 @@ struct Run {
     for (int j = 2; j <= b; ++j) {
       GemmBatch g{fin, s, 0};
       for (int r = 0; r < R; ++r)
-        for (int m = 0; m < 4; ++m) g.add(Ypf(r, m, j - 1), Ypf(r, m, 1), G(r, m), n, L);
+        for (int m = 0; m < nexp; ++m) g.add(Ypf(r, m, j - 1), Ypf(r, m, 1), G(r, m), n, L);
       g.flush();
       if (g.status) return g.status;
       RetruncBatch rt{&l, fout, fin, s};
       rt.a.nadd = 0;
       rt.a.idcoef = make_double2(0.0, 0.0);
       for (int r = 0; r < R; ++r)
-        for (int m = 0; m < 4; ++m) rt.add(G(r, m), Ypf(r, m, j), Ypt(r, m, j), nullptr, 0);
+        for (int m = 0; m < nexp; ++m) rt.add(G(r, m), Ypf(r, m, j), Ypt(r, m, j), nullptr, 0);
       rt.flush();
       if (rt.status) return rt.status;
     }
@@ -749,7 +861,7 @@ struct Run {
           return e;
         };
         for (int r = 0; r < R; ++r)
-          for (int m = 0; m < 4; ++m) {
+          for (int m = 0; m < nexp; ++m) {
             if (fw.njobs == kMaxTransformJobs) { pm_status e = flush(); if (e) return e; }
             FwdJob& j = fw.jobs[fw.njobs++];
             j.src = Ypt(r, m, b);
@@ -768,7 +880,7 @@ struct Run {
         if (q < Q) {
           GemmBatch g{fin, s, 0};
           for (int r = 0; r < R; ++r)
-            for (int m = 0; m < 4; ++m) g.add(ybf(r, m, lprod), Zf(r, m), G(r, m), n, lprod);
+            for (int m = 0; m < nexp; ++m) g.add(ybf(r, m, lprod), Zf(r, m), G(r, m), n, lprod);
           g.flush();
           if (g.status) return g.status;
         }
@@ -780,7 +892,7 @@ struct Run {
         for (int i = 1; i < b; ++i) rt.a.coef[i - 1] = make_double2(cfac(q * b + i), 0.0);
         rt.a.idcoef = make_double2(cfac(q * b), 0.0);
         for (int r = 0; r < R; ++r)
-          for (int m = 0; m < 4; ++m)
+          for (int m = 0; m < nexp; ++m)
             rt.add(q < Q ? static_cast<const void*>(G(r, m)) : nullptr, Zf(r, m), nullptr,
                    b > 1 ? Ypt(r, m, 1) : nullptr, ystride);
         rt.flush();
@@ -808,11 +920,28 @@ struct Run {
         }
       pm_status e = st(timed(PM_PHASE_FORWARD, s, [&] { return launch_forward(fa, L, E, fin, s); }));
       if (e) return e;
+      auto ez = [&](int r, int m) { return Zf(r, nexp == 1 ? 0 : m); };
       GemmBatch g{fin, s, 0};
       for (int r = 0; r < R; ++r)
-        for (int m = 0; m < 4; ++m) g.add(Zf(r, m), Ut(r, m), G(r, m), n, L);
+        for (int m = 0; m < 4; ++m) g.add(ez(r, m), Ut(r, m), G(r, m), n, L);
       g.flush();
       if (g.status) return g.status;
+      if (conj_update) {
+        // (E U_m) re-truncated in Fourier space, then times E^+ (the
+        // conjugated operand: mode (L - p) mod L, conjugate-transposed)
+        RetruncBatch rt{&l, fout, fin, s};
+        rt.a.nadd = 0;
+        rt.a.idcoef = make_double2(0.0, 0.0);
+        for (int r = 0; r < R; ++r)
+          for (int m = 0; m < 4; ++m) rt.add(G(r, m), Xt(r, 4 + m), nullptr, nullptr, 0);
+        rt.flush();
+        if (rt.status) return rt.status;
+        GemmBatch gc{fin, s, 1};
+        for (int r = 0; r < R; ++r)
+          for (int m = 0; m < 4; ++m) gc.add(Xt(r, 4 + m), ez(r, m), G(r, m), n, L);
+        gc.flush();
+        if (gc.status) return gc.status;
+      }
       CombineArgs ca{};
       for (int r = 0; r < R; ++r)
         for (int m = 0; m < 4; ++m) {
@@ -865,6 +994,25 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
   pm_status e = run.links_forward();
   if (!e) e = run.staples();
   if (!e) e = run.force(static_cast<const double2*>(eta), nullptr, 0.0, 0.0, true);
+  if (!e) e = run.exp_and_update();
+  return e;
+}
+
+pm_status nspt_gauge(void* U, int R, const nspt_params* p, double alpha, int prec, void* workspace,
+                     size_t workspace_bytes, hipStream_t s) {
+  if (!valid_params(R, p, prec)) return PM_ERR_INVALID;
+  if (!U || !workspace || !std::isfinite(alpha) || alpha < 0.0) return PM_ERR_INVALID;
+  if (reinterpret_cast<uintptr_t>(U) % 16 || reinterpret_cast<uintptr_t>(workspace) % kAlign) return PM_ERR_INVALID;
+  const Layout l = layout(R, p, prec);
+  if (workspace_bytes < l.total) return PM_ERR_WORKSPACE;
+  const size_t ub = static_cast<size_t>(R) * 4 * l.nord * l.E * 16;
+  if (overlaps(workspace, l.total, U, ub)) return PM_ERR_INVALID;
+  if (alpha == 0.0) return PM_OK;   // Omega = 1
+  Run run(U, R, p, prec, workspace, s);
+  run.nexp = 1;
+  run.conj_update = true;
+  pm_status e = run.links_forward();
+  if (!e) e = run.gauge_exponent(alpha);
   if (!e) e = run.exp_and_update();
   return e;
 }

@@ -29,7 +29,7 @@ struct RetruncArgs {
 };
 
 // Inverse transform of sum_q coef[q] * src[q], unscaled, orders kmin..nord-1.
-constexpr int kMaxCombine = 6;
+constexpr int kMaxCombine = 8;
 struct CombineJob {
   const void* src[kMaxCombine];
   double2 coef[kMaxCombine];
@@ -40,7 +40,7 @@ struct CombineJob {
   int nord;
   int kmin;
 };
-constexpr int kMaxCombineJobs = 16;
+constexpr int kMaxCombineJobs = 12;
 struct CombineArgs { CombineJob jobs[kMaxCombineJobs]; int njobs; };
 
 struct TraceJob {
@@ -54,7 +54,7 @@ struct TraceArgs { TraceJob jobs[kMaxTransformJobs]; int njobs; };
 struct ForceJob {
   const double2* M;        // [nord][n][n], unscaled
   const double2* tr;       // [nord] traces of M
-  const double2* eta;      // [n][n] noise (Langevin form)
+  const double2* eta;      // [n][n] noise (Langevin form), or null for none
   double2* P;              // [nord][n][n] momentum series, updated (MD form)
   double2* Y;              // [nord][n][n] output, multiplied by s^k, or null (MD form only)
   const ScaleRec* rec;

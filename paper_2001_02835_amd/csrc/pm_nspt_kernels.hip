@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs args) {
         y = make_double2(-args.dt * pv.y, args.dt * pv.x);
       } else {
         y = make_double2(-eps * d.x, -eps * d.y);     // i X = -eps (D - Tr D / N)
-        if (k == 1) {
+        if (k == 1 && jb.eta) {
           const double2 et = jb.eta[static_cast<size_t>(i) * n + j];
           y = make_double2(y.x - noise * et.y, y.y + noise * et.x);   // + i sqrt(2 eps) eta
         }
@@ -275,13 +275,14 @@ hipError_t launch_inv_combine(const CombineArgs& a, int L, int max_entries, Four
   if (a.njobs <= 0) return hipSuccess;
   const int ent = fft_entries_per_group(L);
   dim3 g((max_entries + ent - 1) / ent, a.njobs);
-  // every job of one launch has the same number of sources (1 or kMaxCombine)
+  // every job of one launch has the same number of sources (1, 6 or 8)
   const int ns = a.jobs[0].nsrc;
   for (int j = 1; j < a.njobs; ++j)
     if (a.jobs[j].nsrc != ns) return hipErrorInvalidValue;
+  static_assert(kMaxCombine == 8, "source counts instantiated below");
   if (ns == 1) return fin == kF64 ? combine_dispatch<kF64, 1>(a, L, g, s) : combine_dispatch<kF32, 1>(a, L, g, s);
-  if (ns == kMaxCombine)
-    return fin == kF64 ? combine_dispatch<kF64, kMaxCombine>(a, L, g, s) : combine_dispatch<kF32, kMaxCombine>(a, L, g, s);
+  if (ns == 6) return fin == kF64 ? combine_dispatch<kF64, 6>(a, L, g, s) : combine_dispatch<kF32, 6>(a, L, g, s);
+  if (ns == 8) return fin == kF64 ? combine_dispatch<kF64, 8>(a, L, g, s) : combine_dispatch<kF32, 8>(a, L, g, s);
   return hipErrorInvalidValue;
 }
 

@@ -126,14 +126,16 @@ __global__ __launch_bounds__(64) void k_scale(ScaleArgs args) {
     double na = 0.0, nb = 0.0;
     if (tid < nord) {
       double sa[4] = {0.0, 0.0, 0.0, 0.0}, sb[4] = {0.0, 0.0, 0.0, 0.0};
+      const int nsb = jb.nser_b > 0 ? jb.nser_b : jb.nser;
       for (int q = 0; q < jb.nser; ++q) {
         const double* pa = jb.partA + (q * nord + tid) * kNormChunks;
+#pragma unroll
+        for (int c = 0; c < kNormChunks; ++c) sa[c & 3] += pa[c];
+      }
+      for (int q = 0; q < nsb; ++q) {
         const double* pb = jb.partB + (q * nord + tid) * kNormChunks;
 #pragma unroll
-        for (int c = 0; c < kNormChunks; ++c) {
-          sa[c & 3] += pa[c];
-          sb[c & 3] += pb[c];
-        }
+        for (int c = 0; c < kNormChunks; ++c) sb[c & 3] += pb[c];
       }
       na = sqrt((sa[0] + sa[1]) + (sa[2] + sa[3]));
       nb = sqrt((sb[0] + sb[1]) + (sb[2] + sb[3]));

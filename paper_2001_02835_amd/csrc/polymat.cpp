@@ -573,6 +573,12 @@ pm_status nspt_wilson_loop(const void* U, int replicas, const nspt_params* param
                          static_cast<hipStream_t>(stream));
 }
 
+pm_status nspt_gauge_fix(void* U, int replicas, const nspt_params* params, double alpha, int precision,
+                         void* workspace, size_t workspace_bytes, void* stream) {
+  return pm::nspt_gauge(U, replicas, params, alpha, precision, workspace, workspace_bytes,
+                        static_cast<hipStream_t>(stream));
+}
+
 pm_status nspt_md_trajectory(void* U, void* P, const void* eta, int replicas, const nspt_params* params,
                              int nsteps, int precision, void* workspace, size_t workspace_bytes,
                              void* stream) {

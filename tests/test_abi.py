@@ -188,3 +188,20 @@ def test_wilson_loop_rejects_bad_arguments():
     assert f(1, 5) == nat.PM_ERR_INVALID
     assert f(2, 2, W=None) == nat.PM_ERR_INVALID
     assert f(2, 2, nb=need - 1) == nat.PM_ERR_WORKSPACE
+
+
+def test_gauge_fix_rejects_bad_arguments():
+    lib = pm.lib()
+    good = nat.NsptParams(9, 3, 1, 7, 0.01)
+    need = lib.nspt_workspace_size(1, ctypes.byref(good), 0)
+    f = lambda U=FAKE_A, alpha=0.1, prm=good, ws=FAKE_WS, nb=need: lib.nspt_gauge_fix(U, 1, ctypes.byref(prm), alpha,
+                                                                                      0, ws, nb, None)
+    assert f(alpha=-0.1) == nat.PM_ERR_INVALID
+    assert f(alpha=float("nan")) == nat.PM_ERR_INVALID
+    assert f(alpha=float("inf")) == nat.PM_ERR_INVALID
+    assert f(U=None) == nat.PM_ERR_INVALID
+    assert f(U=FAKE_A + 8) == nat.PM_ERR_INVALID                                   # misaligned
+    assert f(U=FAKE_WS) == nat.PM_ERR_INVALID                                      # U overlaps the workspace
+    assert f(nb=need - 1) == nat.PM_ERR_WORKSPACE
+    assert f(prm=nat.NsptParams(10, 3, 1, 7, 0.01)) == nat.PM_ERR_INVALID          # n != L^2
+    assert f(alpha=0.0) == nat.PM_OK                                               # Omega = 1: nothing to do
