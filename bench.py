@@ -278,6 +278,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-extra", action="store_true", help="skip the ntrunc = 63 precision lines")
+    ap.add_argument("--precision-only", action="store_true",
+                    help="of the extra lines, run only the ntrunc = 63 precision comparison")
     ap.add_argument("--nspt-steps", type=int, default=3)
     ap.add_argument("--md-steps", type=int, default=4, help="leapfrog steps of the timed MD trajectory")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -362,7 +364,7 @@ def main(argv=None):
         out["ntrunc63"] = {"workload": "1 product N=225 ntrunc=63 (L=128), entries N(0,1)*1.3^k, auto rescale",
                            **extra}
 
-    if not args.no_extra:
+    if not args.no_extra and not args.precision_only:
         out["batched_uneven"] = bench_uneven(torch, synth, pm, dev, max(args.steps // 20, 3))
         out["nspt_step"] = bench_nspt(torch, synth, pm, dev, args.nspt_steps)
         out["nspt_md"] = bench_md(torch, synth, pm, dev, args.md_steps)
