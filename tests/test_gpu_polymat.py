@@ -59,6 +59,26 @@ def test_ragged_shapes_fp64(n, nt):
     assert e.max() < TOL["fp64"], e
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("n", [1, 2, 5, 8, 9, 31, 32, 63, 64, 65, 100, 130])
+def test_ragged_shapes_reduced_precisions_all_operand_forms(prec, n):
+    """Ragged tiles and row pitches (split-BF16 rows padded to a multiple of
+    8 entries, contracted index on either side of the transposing LDS read)
+    for the four operand forms X, X^+ on either side."""
+    nt = 5
+    items, refs = [], []
+    for i in range(4):
+        a, b = rs(100 + i, n, nt, 0.8), rs(110 + i, n, nt, 0.8)
+        op_a, op_b = i % 2, i // 2
+        refs.append(ser.star(ser.dagger(a) if op_a else a, ser.dagger(b) if op_b else b))
+        items.append(dict(A=to_dev(a), B=to_dev(b), C=torch.empty((nt + 1, n, n), dtype=torch.complex128, device=DEV),
+                          op_a=op_a, op_b=op_b, scale=0.0))
+    pm.polymat_mul_batched(items, precision=prec)
+    for i, (it, ref) in enumerate(zip(items, refs)):
+        e = order_errors(to_host(it["C"]), ref)
+        assert e.max() < TOL[prec], (i, e)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("n,nt,r", [(33, 7, 1.0), (70, 31, 0.5), (48, 63, 1.3)])
 def test_precisions_with_auto_rescale(prec, n, nt, r):
