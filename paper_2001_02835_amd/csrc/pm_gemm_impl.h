@@ -293,6 +293,11 @@ struct Tile2 {
   static constexpr size_t kLdsBytes = sizeof(T2) * (kAElems + kBElems);
 };
 
+// Eight wavefronts of 2 blocks each: built for four wavefronts per SIMD, so
+// that two work-groups share a CU (their LDS fits twice).
+template <int WM, int WN, int WGM, int WGN>
+constexpr int cgemm2_min_waves() { return (WM * WN <= 2 && WGM * WGN == 8) ? 4 : 1; }
+
 // CONV selects the direct form of eq. (5) instead of a Fourier mode: p is an
 // output order k, A and B are time-domain series [L = ntrunc+1][n][n], and
 // the contraction runs over (l, kk) for l = 0..k: C^(k) = sum_l opA(A)^(l)
@@ -340,12 +345,21 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
     if (!OPB) { b_j[u] = q % BN; b_k[u] = q / BN; } else { b_k[u] = q % BK; b_j[u] = q / BK; }
   }
 
-  T2 ra[G::LA], rb[G::LB];
-  bool oka[G::LA], okb[G::LB];
+  // register stages of the global loads.  With two (the 2-block, 8-wavefront
+  // shapes, which fit in 128 registers) the loads of chunk c + 2 are in
+  // flight while chunk c is multiplied and chunk c + 1 goes to LDS; with one
+  // the loads run one chunk ahead.
+  constexpr bool PF2 = cgemm2_min_waves<WM, WN, WGM, WGN>() == 4;
+  constexpr int D = PF2 ? 2 : 1;
+  struct Stage {
+    T2 ra[G::LA], rb[G::LB];
+    bool oka[G::LA], okb[G::LB];
+  };
+  Stage st0, st1;
   // chunk c: its k offset within the current term, and (CONV) the term's
   // operand orders l and p - l
   auto chunk_k0 = [&](int c) { return CONV ? (c - (c / cpl) * cpl) * BK : c * BK; };
-  auto load_chunk = [&](int c) {
+  auto load_chunk = [&](int c, Stage& S) {
     const int k0 = chunk_k0(c);
     const T2* __restrict__ Ac = Ag;
     const T2* __restrict__ Bc = Bg;
@@ -359,31 +373,31 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
       const int gi = row0 + a_i[u], gk = k0 + a_k[u];
       const bool ok = gi < n && gk < n;
       const int off = ok ? (OPA ? gk * n + gi : gi * n + gk) : 0;
-      ra[u] = Ac[off];
-      oka[u] = ok;
+      S.ra[u] = Ac[off];
+      S.oka[u] = ok;
     }
 #pragma unroll
     for (int u = 0; u < G::LB; ++u) {
       const int gj = col0 + b_j[u], gk = k0 + b_k[u];
       const bool ok = gj < n && gk < n;
       const int off = ok ? (OPB ? gj * n + gk : gk * n + gj) : 0;
-      rb[u] = Bc[off];
-      okb[u] = ok;
+      S.rb[u] = Bc[off];
+      S.okb[u] = ok;
     }
   };
-  auto store_chunk = [&](int buf) {
+  auto store_chunk = [&](int buf, const Stage& S) {
 #pragma unroll
     for (int u = 0; u < G::LA; ++u) {
       T2 v;
-      v.x = oka[u] ? ra[u].x : T(0);
-      v.y = oka[u] ? (OPA ? -ra[u].y : ra[u].y) : T(0);
+      v.x = S.oka[u] ? S.ra[u].x : T(0);
+      v.y = S.oka[u] ? (OPA ? -S.ra[u].y : S.ra[u].y) : T(0);
       As[buf][a_k[u]][a_i[u]] = v;
     }
 #pragma unroll
     for (int u = 0; u < G::LB; ++u) {
       T2 v;
-      v.x = okb[u] ? rb[u].x : T(0);
-      v.y = okb[u] ? (OPB ? -rb[u].y : rb[u].y) : T(0);
+      v.x = S.okb[u] ? S.rb[u].x : T(0);
+      v.y = S.okb[u] ? (OPB ? -S.rb[u].y : S.rb[u].y) : T(0);
       Bs[buf][b_k[u]][b_j[u]] = v;
     }
   };
@@ -493,13 +507,13 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
   };
 
   const int nchunks = CONV ? (p + 1) * cpl : cpl;
-  load_chunk(0);
-  store_chunk(0);
-  __syncthreads();
-  for (int c = 0; c < nchunks; ++c) {
+  // one chunk: cur holds chunk c + 1 (stored to the other LDS buffer after
+  // the products), nxt receives the loads of chunk c + D (with one stage
+  // both are the same registers)
+  auto chunk = [&](int c, const Stage& cur, Stage& nxt) {
     const int buf = c & 1;
     const int k0 = chunk_k0(c);
-    if (c + 1 < nchunks) load_chunk(c + 1);
+    if (c + D < nchunks) load_chunk(c + D, nxt);
     // k-step s of the chunk contracts k = k0 + 4 g + s; it is needed when k0 + s < n
     T2 fa0[WM], fb0[WN], fa1[WM], fb1[WN];
     read_frags(buf, 0, fa0, fb0);
@@ -514,8 +528,23 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
         if (k0 + 3 < n) mma(fa1, fb1);
       }
     }
-    if (c + 1 < nchunks) store_chunk(buf ^ 1);
+    if (c + 1 < nchunks) store_chunk(buf ^ 1, cur);
     __syncthreads();
+  };
+  load_chunk(0, st0);
+  store_chunk(0, st0);
+  if constexpr (PF2) {
+    if (nchunks > 1) load_chunk(1, st1);
+  }
+  __syncthreads();
+  if constexpr (PF2) {
+    // pairs of chunks, so that the two stages keep fixed registers
+    for (int c = 0; c < nchunks; c += 2) {
+      chunk(c, st1, st0);
+      if (c + 1 < nchunks) chunk(c + 1, st0, st1);
+    }
+  } else {
+    for (int c = 0; c < nchunks; ++c) chunk(c, st0, st0);
   }
 
 #pragma unroll
@@ -580,7 +609,7 @@ __device__ __forceinline__ void gemm_task(const GemmJob* jobs, int njobs, int id
 }
 
 template <typename T, int WM, int WN, int WGM, int WGN, bool OPA, bool OPB, bool G3, bool CONV = false>
-__global__ __launch_bounds__(kWave * WGM * WGN) void k_cgemm2(GemmArgs args) {
+__global__ __launch_bounds__(kWave * WGM * WGN, (cgemm2_min_waves<WM, WN, WGM, WGN>())) void k_cgemm2(GemmArgs args) {
   __shared__ __attribute__((aligned(16))) char smem[Tile2<T, WM, WN, WGM, WGN>::kLdsBytes];
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   int jidx, p, tm, tn;
