@@ -66,3 +66,25 @@ def test_langevin_step_graph_replays():
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(u, eager), rep
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_gauge_fix_graph_replays(prec):
+    L, k, nt, R = 5, 2, 7, 2
+    u0 = to_dev(series_links(L, k, nt, 0.6, 63, replicas=R))
+    prm = pm.nspt_params(L, k, nt, 0.02)
+    ws = pm.workspace(pm.nspt_workspace_size(R, prm, prec), DEV)
+    u = u0.clone()
+    pm.nspt_gauge_fix(u, prm, 0.1, prec, ws=ws)
+    torch.cuda.synchronize()
+    eager = u.clone()
+    g = _capture(lambda: pm.nspt_gauge_fix(u, prm, 0.1, prec, ws=ws))
+    for rep in range(3):
+        u.copy_(u0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(u, eager), rep
+        v = u0.clone()
+        pm.nspt_gauge_fix(v, prm, 0.1, prec, ws=ws)      # eager work between replays
+        torch.cuda.synchronize()

@@ -254,3 +254,16 @@ def test_maximum_matrix_size_sampled(prec):
         ref = sum(np.dot(x, y) for x, y in terms)
         scale = sum(np.linalg.norm(x) * np.linalg.norm(y) for x, y in terms)
         assert abs(got[t] - ref) <= TOL[prec] * scale, (prec, k, i, j, got[t], ref)
+
+
+def test_batched_output_aliasing_another_problems_input():
+    """C of one problem is the A of another: every A and B is read before any
+    C is written, so the second product uses the original contents."""
+    n, nt = 40, 7
+    a0, b0, x, b1 = (rs(130 + i, n, nt, 0.8) for i in range(4))
+    dx = to_dev(x)
+    items = [dict(A=to_dev(a0), B=to_dev(b0), C=dx),
+             dict(A=dx, B=to_dev(b1), C=torch.empty_like(dx))]
+    pm.polymat_mul_batched(items)
+    assert order_errors(to_host(items[0]["C"]), ser.star(a0, b0)).max() < TOL["fp64"]
+    assert order_errors(to_host(items[1]["C"]), ser.star(x, b1)).max() < TOL["fp64"]
