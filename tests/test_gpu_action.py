@@ -32,7 +32,7 @@ def _scale(u):
     return b
 
 
-@pytest.mark.parametrize("L,k,nt,R", [(3, 1, 7, 2), (5, 2, 15, 1), (9, 2, 31, 1)])
+@pytest.mark.parametrize("L,k,nt,R", [(3, 1, 7, 2), (5, 2, 15, 1), (9, 2, 31, 1), (3, 1, 63, 1)])
 def test_action_matches_oracle(L, k, nt, R):
     u = series_links(L, k, nt, 0.6, 40 + L, replicas=R)
     z = tek.twist_tensor(L, k)

@@ -24,7 +24,7 @@ def _gpu_fix(u, L, k, nt, alpha, prec="fp64"):
 
 
 @pytest.mark.parametrize("L,k,nt,R", [(3, 1, 5, 2), (5, 2, 7, 1), (3, 1, 1, 1), (3, 1, 0, 1), (5, 1, 15, 1),
-                                      (7, 2, 31, 1), (1, 0, 3, 1)])
+                                      (7, 2, 31, 1), (1, 0, 3, 1), (3, 1, 63, 1)])
 def test_gauge_fix_matches_oracle(L, k, nt, R):
     u = series_links(L, k, nt, 0.6, 21, replicas=R)
     got = _gpu_fix(u, L, k, nt, ALPHA)

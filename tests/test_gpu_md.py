@@ -48,7 +48,7 @@ def _check(got, ref, tol, what):
 
 
 @pytest.mark.parametrize("L,k,nt,R,nsteps", [(3, 1, 5, 2, 3), (5, 2, 7, 1, 2), (3, 1, 1, 1, 2), (5, 1, 15, 1, 2),
-                                             (7, 2, 31, 1, 2), (9, 2, 31, 1, 2), (1, 0, 3, 1, 2)])
+                                             (7, 2, 31, 1, 2), (9, 2, 31, 1, 2), (1, 0, 3, 1, 2), (3, 1, 63, 1, 1)])
 def test_trajectory_matches_oracle(L, k, nt, R, nsteps):
     dt = 0.1
     u, eta = _inputs(L, k, nt, R, 1)

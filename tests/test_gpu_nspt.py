@@ -23,7 +23,7 @@ def gpu_step(u, eta, L, k, nt, eps, prec="fp64"):
 
 
 @pytest.mark.parametrize("L,k,nt,R", [(3, 1, 7, 2), (5, 2, 5, 1), (3, 1, 0, 1), (3, 1, 1, 1), (5, 1, 15, 1),
-                                      (1, 0, 3, 1)])
+                                      (1, 0, 3, 1), (7, 2, 31, 1), (3, 1, 63, 1)])
 def test_step_matches_oracle(L, k, nt, R):
     eps = 0.05
     u = series_links(L, k, nt, 0.6, L * 100 + nt, replicas=R)
