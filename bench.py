@@ -351,7 +351,8 @@ def main(argv=None):
         for prec in ("fp64", "fp32", "bf16x3"):
             try:
                 ws3 = pm.workspace(pm.batched_workspace_size(items3, prec), dev)
-                ms3, ph3 = time_steps(torch, pm, items3, prec, max(args.steps // 4, 10), 3, ws3, timing=True)
+                st3 = max(args.steps // 4, 10)
+                ms3, ph3 = time_steps(torch, pm, items3, prec, st3, 3, ws3, timing=True)
                 pms3, pl3 = ph3["product"]
                 fl3 = pm.transform_length(nt3) * 8.0 * n3 ** 3
                 ach = fl3 / (pms3 * 1e-3 / max(pl3, 1)) / 1e12
@@ -364,7 +365,8 @@ def main(argv=None):
                                "product_kernel_useful_tflops": round(ach, 2),
                                "product_kernel_issued_tflops": round(issued, 2),
                                "product_kernel_frac_of_peak": round(ach / PEAK[prec], 4),
-                               "product_kernel_issued_frac_of_peak": round(issued / PEAK[prec], 4)}
+                               "product_kernel_issued_frac_of_peak": round(issued / PEAK[prec], 4),
+                               "phase_ms_per_mult": {k: round(v[0] / st3, 4) for k, v in ph3.items() if v[1]}}
                 del ws3
             except Exception as exc:   # a precision that is not built reports why
                 extra[prec] = {"error": str(exc)}
