@@ -123,8 +123,9 @@ def bench_uneven(torch, synth, pm, dev, steps):
 
 def bench_nspt(torch, synth, pm, dev, steps):
     """NSPT Euler-Langevin step: 8 replicas x 4 links, SU(225) (L=15, k=4), ntrunc=31,
-    eps=0.01, started at the twisted vacuum and evolved by warm-up steps; then one
-    stochastic gauge-fixing step (alpha = 0.1) on the same links."""
+    eps=0.01, started at the twisted vacuum and evolved by warm-up steps; the same
+    step replayed from a captured HIP graph; then one stochastic gauge-fixing step
+    (alpha = 0.1) on the same links."""
     import numpy as np
     L, k, nt, eps, R = 15, 4, 31, 0.01, 8
     n = L * L
@@ -154,6 +155,28 @@ def bench_nspt(torch, synth, pm, dev, steps):
         torch.cuda.synchronize()
         pm.timing_enable(False)
         ph = pm.timing_read()
+        # the same step captured once into a HIP graph and replayed
+        try:
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                pm.nspt_langevin_step(u, noise[0], prm, prec, ws=ws)
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                pm.nspt_langevin_step(u, noise[0], prm, prec, ws=ws)
+            graph.replay()
+            torch.cuda.synchronize()
+            e0.record()
+            for i in range(steps):
+                graph.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            graph_ms = round(e0.elapsed_time(e1) / steps, 3)
+            del graph
+        except Exception as exc:   # report, do not fail the bench line
+            graph_ms = f"capture failed: {exc}"
         # one stochastic gauge-fixing step (alpha = 0.1) on the evolved links
         pm.nspt_gauge_fix(u, prm, 0.1, prec, ws=ws)
         torch.cuda.synchronize()
@@ -166,7 +189,7 @@ def bench_nspt(torch, synth, pm, dev, steps):
         res[prec] = {"ms_per_step": round(ms, 3), "steps_per_s": round(1e3 / ms, 3),
                      "replica_steps_per_s": round(R * 1e3 / ms, 2),
                      "phase_ms_per_step": {kk: round(v[0] / steps, 3) for kk, v in ph.items() if v[1]},
-                     "gauge_fix_ms": round(gms, 3)}
+                     "graph_ms_per_step": graph_ms, "gauge_fix_ms": round(gms, 3)}
         del ws
     return res
 
