@@ -29,6 +29,8 @@ struct RetruncArgs {
 };
 
 // Inverse transform of sum_q coef[q] * src[q], unscaled, orders kmin..nord-1.
+// nsrc is 1, 6 or 8 (the instantiated source counts), the same for every job
+// of a launch.
 constexpr int kMaxCombine = 8;
 struct CombineJob {
   const void* src[kMaxCombine];
