@@ -1,7 +1,8 @@
 """C-ABI checks that need no GPU: the library loads, exports every function
 include/polymat.h declares, and rejects bad arguments on the host before it
-touches the device (every call below fails validation, so nothing is ever
-enqueued and no pointer is dereferenced)."""
+touches the device (every call below fails validation or, for a zero
+gauge-fixing step, returns before any work, so nothing is ever enqueued and
+no pointer is dereferenced)."""
 import ctypes
 import os
 import re
@@ -205,3 +206,18 @@ def test_gauge_fix_rejects_bad_arguments():
     assert f(nb=need - 1) == nat.PM_ERR_WORKSPACE
     assert f(prm=nat.NsptParams(10, 3, 1, 7, 0.01)) == nat.PM_ERR_INVALID          # n != L^2
     assert f(alpha=0.0) == nat.PM_OK                                               # Omega = 1: nothing to do
+
+
+def test_limits_of_counts_and_sizes():
+    lib = pm.lib()
+    good = nat.NsptParams(9, 3, 1, 7, 0.01)
+    assert lib.nspt_workspace_size(1024, ctypes.byref(good), 0) > 0
+    assert lib.nspt_workspace_size(1025, ctypes.byref(good), 0) == 0            # more than 1024 replicas
+    assert lib.polymat_workspace_size(4096, 0, nat.PM_PREC_FP64, 1) > 0            # largest matrix
+    assert lib.polymat_workspace_size(4097, 0, nat.PM_PREC_FP64, 1) == 0
+    assert lib.polymat_workspace_size(9, 7, nat.PM_PREC_FP64, 4097) == 0           # batch above the limit
+    arr = (nat.PmProblem * 1)()
+    arr[0].A, arr[0].B, arr[0].C = FAKE_A, FAKE_B, FAKE_C
+    arr[0].n, arr[0].ntrunc = 9, 7
+    assert lib.polymat_batched_workspace_size(arr, 4097, 0) == 0
+    assert lib.polymat_mul_batched(arr, 4097, 0, FAKE_WS, 1 << 40, None) == nat.PM_ERR_INVALID
