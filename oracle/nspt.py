@@ -248,3 +248,85 @@ def gauge_fix(u: np.ndarray, alpha: float) -> np.ndarray:
 def gauge_fix_replicas(u: np.ndarray, alpha: float) -> np.ndarray:
     """Replica batch: u [R, 4, ntrunc+1, N, N]."""
     return np.stack([gauge_fix(u[r], alpha) for r in range(u.shape[0])])
+
+
+# --------------------------------------------------------------------------
+# Noise drawn from a counter-based generator, so that the device and this
+# oracle draw the same Gaussian noise from (seed, step) (an optional form of
+# the Langevin step; the paper does not say how its noise is generated).
+#
+# Generator: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11), restated from
+# its definition.  Per step t, replica r, direction mu and entry pair i <= j
+# of the N x N matrix: counter (i N + j, 4 r + mu, t, 0), key (seed, 0).
+# Of the four 64-bit outputs x0, x1: u_a = ((x0 >> 11) + 1) 2^-53 in (0, 1],
+# u_b = (x1 >> 11) 2^-53 in [0, 1); Box-Muller rho = sqrt(-2 ln u_a),
+# z0 = rho cos(2 pi u_b), z1 = rho sin(2 pi u_b).  eta_ij = (z0 + i z1)/sqrt(2)
+# and eta_ji = conj(eta_ij) for i < j, eta_ii = z0; then the trace is removed
+# from the diagonal (the GUE-traceless recipe of the Langevin noise).
+# --------------------------------------------------------------------------
+
+_PHILOX_M = (0xD2E7470EE14C6C93, 0xCA5A826395121157)
+_PHILOX_W = (0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B)
+_MASK64 = (1 << 64) - 1
+
+
+def _mulhilo(a: np.ndarray, m: int):
+    """64 x 64 -> 128-bit product of uint64 arrays a and the constant m, as (hi, lo)."""
+    a = a.astype(np.uint64)
+    a_lo, a_hi = a & np.uint64(0xFFFFFFFF), a >> np.uint64(32)
+    m_lo, m_hi = np.uint64(m & 0xFFFFFFFF), np.uint64(m >> 32)
+    p0 = a_lo * m_lo
+    p1 = a_lo * m_hi
+    p2 = a_hi * m_lo
+    p3 = a_hi * m_hi
+    mid = (p0 >> np.uint64(32)) + (p1 & np.uint64(0xFFFFFFFF)) + (p2 & np.uint64(0xFFFFFFFF))
+    hi = p3 + (p1 >> np.uint64(32)) + (p2 >> np.uint64(32)) + (mid >> np.uint64(32))
+    lo = a * np.uint64(m)          # wraps modulo 2^64
+    return hi, lo
+
+
+def philox4x64(counter, key, rounds: int = 10):
+    """Philox4x64 of counter (4 uint64 arrays) under key (2 uint64 arrays)."""
+    c = [np.asarray(x, dtype=np.uint64) for x in counter]
+    k = [np.asarray(x, dtype=np.uint64) for x in key]
+    with np.errstate(over="ignore"):
+        for _ in range(rounds):
+            hi0, lo0 = _mulhilo(c[0], _PHILOX_M[0])
+            hi1, lo1 = _mulhilo(c[2], _PHILOX_M[1])
+            c = [hi1 ^ c[1] ^ k[0], lo1, hi0 ^ c[3] ^ k[1], lo0]
+            k = [k[0] + np.uint64(_PHILOX_W[0]), k[1] + np.uint64(_PHILOX_W[1])]
+    return c
+
+
+def philox_noise(seed: int, step: int, replicas: int, n: int) -> np.ndarray:
+    """Hermitian traceless noise complex128 [replicas, 4, n, n] of step `step`."""
+    i, j = np.triu_indices(n)
+    out = np.zeros((replicas, 4, n, n), dtype=np.complex128)
+    for r in range(replicas):
+        for mu in range(4):
+            ctr = [(i * n + j).astype(np.uint64), np.full(i.shape, 4 * r + mu, np.uint64),
+                   np.full(i.shape, step, np.uint64), np.zeros(i.shape, np.uint64)]
+            x = philox4x64(ctr, [np.full(i.shape, seed, np.uint64), np.zeros(i.shape, np.uint64)])
+            ua = ((x[0] >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
+            ub = (x[1] >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+            rho = np.sqrt(-2.0 * np.log(ua))
+            z0, z1 = rho * np.cos(2.0 * np.pi * ub), rho * np.sin(2.0 * np.pi * ub)
+            e = np.zeros((n, n), dtype=np.complex128)
+            off = i < j
+            e[i[off], j[off]] = (z0[off] + 1j * z1[off]) / np.sqrt(2.0)
+            e[j[off], i[off]] = (z0[off] - 1j * z1[off]) / np.sqrt(2.0)
+            d = ~off
+            e[i[d], i[d]] = z0[d]
+            e -= np.trace(e) / n * np.eye(n)
+            out[r, mu] = e
+    return out
+
+
+def langevin_steps_philox(u: np.ndarray, z: np.ndarray, eps: float, seed: int, step0: int,
+                          nsteps: int) -> np.ndarray:
+    """nsteps Langevin steps of a replica batch u [R, 4, ntrunc+1, N, N] with
+    the noise of steps step0 .. step0 + nsteps - 1."""
+    for t in range(step0, step0 + nsteps):
+        eta = philox_noise(seed, t, u.shape[0], u.shape[-1])
+        u = langevin_step_replicas(u, eta, z, eps)
+    return u
