@@ -235,7 +235,8 @@ typedef struct {
   double eps;   /* rescaled Langevin time step, or the MD step dt (> 0) */
 } nspt_params;
 
-/* Workspace bytes for nspt_langevin_step and nspt_md_trajectory, or 0 if invalid. */
+/* Workspace bytes for nspt_langevin_step, nspt_langevin_steps, nspt_md_trajectory and the
+ * other NSPT calls, or 0 if invalid. */
 size_t nspt_workspace_size(int replicas, const nspt_params* params, int precision);
 
 /*
@@ -250,6 +251,37 @@ pm_status nspt_langevin_step(void* U, const void* eta, int replicas,
                              const nspt_params* params, int precision,
                              void* workspace, size_t workspace_bytes,
                              void* stream);
+
+/*
+ * nspt_noise - the Langevin noise of one step drawn on the device from a
+ * counter-based generator, so that a run needs no host-side noise (the
+ * paper does not say how its noise is generated; this is the library's
+ * choice).  For matrix m = 4 r + mu (replica r, direction mu) and entry pair
+ * i <= j: counter (i n + j, m, step, 0) and key (seed, 0) of Philox4x64-10
+ * (Salmon et al., SC'11); of its outputs x0, x1, u_a = ((x0 >> 11) + 1) 2^-53,
+ * u_b = (x1 >> 11) 2^-53, rho = sqrt(-2 ln u_a), z0 = rho cos(2 pi u_b),
+ * z1 = rho sin(2 pi u_b); eta_ij = (z0 + i z1) / sqrt(2) = conj(eta_ji) for
+ * i < j, eta_ii = z0, and finally eta_ii -= Tr(eta) / n.  This is the
+ * Hermitian traceless (GUE) noise of nspt_langevin_step.
+ *   eta       device complex128 [replicas][4][n][n], written.
+ *   replicas  1 .. 1024;  n  1 .. PM_MAX_N.
+ */
+pm_status nspt_noise(void* eta, int replicas, int n, unsigned long long seed,
+                     unsigned long long step, void* stream);
+
+/*
+ * nspt_langevin_steps - nsteps Euler-Langevin steps (those of
+ * nspt_langevin_step) with the noise of nspt_noise for steps step0,
+ * step0 + 1, ..., drawn on the device into the workspace.
+ *   U       device complex128 [replicas][4][ntrunc+1][n][n], updated in place.
+ *   nsteps  1 .. 100000.
+ * The workspace is the one of nspt_langevin_step (nspt_workspace_size); U
+ * and the workspace must not overlap (PM_ERR_INVALID).
+ */
+pm_status nspt_langevin_steps(void* U, int replicas, const nspt_params* params,
+                              unsigned long long seed, unsigned long long step0, int nsteps,
+                              int precision, void* workspace, size_t workspace_bytes,
+                              void* stream);
 
 /*
  * One molecular-dynamics trajectory of the NSPT tower (Section 2, eq. (3)

@@ -8,7 +8,8 @@ from ._native import (PM_OK, PM_ERR_INVALID, PM_ERR_WORKSPACE, PM_ERR_DEVICE, PM
                       LIB_PATH, lib)
 from .api import (polymat_mul, polymat_mul_naive, polymat_mul_batched, batched_workspace_size, workspace_size,
                   forward_transform, inverse_transform, transform_length, nspt_params,
-                  nspt_workspace_size, nspt_langevin_step, nspt_md_trajectory, nspt_gauge_fix, nspt_action,
+                  nspt_workspace_size, nspt_langevin_step, nspt_langevin_steps, nspt_noise, nspt_md_trajectory,
+                  nspt_gauge_fix, nspt_action,
                   nspt_wilson_loop,
                   workspace, timing_enable,
                   timing_read)
@@ -16,5 +17,6 @@ from .api import (polymat_mul, polymat_mul_naive, polymat_mul_batched, batched_w
 __all__ = [
     "polymat_mul", "polymat_mul_naive", "polymat_mul_batched", "batched_workspace_size", "workspace_size",
     "forward_transform", "inverse_transform", "transform_length", "nspt_params",
-    "nspt_workspace_size", "nspt_langevin_step", "nspt_md_trajectory", "nspt_gauge_fix", "nspt_action", "nspt_wilson_loop", "workspace", "timing_enable", "timing_read", "lib", "LIB_PATH", "PolymatError",
+    "nspt_workspace_size", "nspt_langevin_step", "nspt_langevin_steps", "nspt_noise", "nspt_md_trajectory",
+    "nspt_gauge_fix", "nspt_action", "nspt_wilson_loop", "workspace", "timing_enable", "timing_read", "lib", "LIB_PATH", "PolymatError",
 ]

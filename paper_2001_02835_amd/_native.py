@@ -43,6 +43,7 @@ class NsptParams(ctypes.Structure):
 
 # symbol -> (restype, argtypes); the exported set that include/polymat.h declares
 _VP, _SZ, _I, _D = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_double
+_U64 = ctypes.c_ulonglong
 SIGNATURES = {
     "polymat_abi_version": (_I, []),
     "polymat_strerror": (ctypes.c_char_p, [_I]),
@@ -63,6 +64,8 @@ SIGNATURES = {
     "nspt_wilson_loop": (_I, [_VP, _I, ctypes.POINTER(NsptParams), _I, _I, _I, _VP, _VP, _SZ, _VP]),
     "nspt_md_trajectory": (_I, [_VP, _VP, _VP, _I, ctypes.POINTER(NsptParams), _I, _I, _VP, _SZ, _VP]),
     "nspt_gauge_fix": (_I, [_VP, _I, ctypes.POINTER(NsptParams), _D, _I, _VP, _SZ, _VP]),
+    "nspt_noise": (_I, [_VP, _I, _I, _U64, _U64, _VP]),
+    "nspt_langevin_steps": (_I, [_VP, _I, ctypes.POINTER(NsptParams), _U64, _U64, _I, _I, _VP, _SZ, _VP]),
 }
 
 _lib = None

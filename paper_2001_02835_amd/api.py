@@ -207,6 +207,31 @@ def nspt_md_trajectory(U: torch.Tensor, P: torch.Tensor, params: nat.NsptParams,
     return U, P
 
 
+def nspt_noise(replicas: int, n: int, seed: int, step: int, device="cuda:0") -> torch.Tensor:
+    """Counter-based Langevin noise complex128 [replicas, 4, n, n] of one step."""
+    eta = torch.empty((replicas, 4, n, n), dtype=torch.complex128, device=device)
+    st = nat.lib().nspt_noise(eta.data_ptr(), int(replicas), int(n), int(seed), int(step), _stream_ptr(eta.device))
+    nat.check(st, "nspt_noise")
+    return eta
+
+
+def nspt_langevin_steps(U: torch.Tensor, params: nat.NsptParams, seed: int, step0: int, nsteps: int,
+                        precision="fp64", ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """nsteps Langevin steps of U [R, 4, ntrunc+1, n, n] in place, noise drawn on the device."""
+    _series_check(U, "U")
+    R = U.shape[0]
+    p = _prec(precision)
+    need = nat.lib().nspt_workspace_size(R, ctypes.byref(params), p)
+    if need == 0:
+        raise ValueError("invalid NSPT parameters")
+    if ws is None:
+        ws = workspace(need, U.device)
+    st = nat.lib().nspt_langevin_steps(U.data_ptr(), R, ctypes.byref(params), int(seed), int(step0), int(nsteps), p,
+                                       ws.data_ptr(), ws.numel(), _stream_ptr(U.device))
+    nat.check(st, "nspt_langevin_steps")
+    return U
+
+
 def nspt_gauge_fix(U: torch.Tensor, params: nat.NsptParams, alpha: float, precision="fp64",
                    ws: Optional[torch.Tensor] = None) -> torch.Tensor:
     """One stochastic gauge-fixing step of step size alpha on U [R, 4, ntrunc+1, n, n], in place."""

@@ -107,7 +107,7 @@ struct Layout {
   int n, E, nord, L, R, b;
   size_t fin, fout, tser;        // bytes: Fourier (product input), Fourier (product output), time series
   size_t rec, rec2, unit, part, partY, trc;   // small tables
-  size_t Ut, G, Xt, M, Ypt, Ypf, Z;
+  size_t Ut, G, Xt, M, Ypt, Ypf, Z, eta;
   size_t total;
 };
 
@@ -139,6 +139,7 @@ Layout layout(int R, const nspt_params* p, int prec) {
   l.Ypt = off;  off += static_cast<size_t>(4) * R * l.b * l.tser;
   l.Ypf = off;  off += static_cast<size_t>(4) * R * l.b * l.fin;
   l.Z = off;    off += static_cast<size_t>(4) * R * l.fin;
+  l.eta = off;  off += align_up(static_cast<size_t>(4) * R * E * 16);   // noise of nspt_steps
   l.total = off;
   return l;
 }
@@ -995,6 +996,40 @@ pm_status nspt_step(void* U, const void* eta, int R, const nspt_params* p, int p
   if (!e) e = run.staples();
   if (!e) e = run.force(static_cast<const double2*>(eta), nullptr, 0.0, 0.0, true);
   if (!e) e = run.exp_and_update();
+  return e;
+}
+
+pm_status nspt_noise(void* eta, int R, int n, unsigned long long seed, unsigned long long step, hipStream_t s) {
+  if (!eta || R < 1 || R > 1024 || n < 1 || n > PM_MAX_N) return PM_ERR_INVALID;
+  if (reinterpret_cast<uintptr_t>(eta) % 16) return PM_ERR_INVALID;
+  NoiseArgs na{};
+  na.eta = static_cast<double2*>(eta);
+  na.seed = seed;
+  na.step = step;
+  na.n = n;
+  na.count = 4 * R;
+  return st(timed(PM_PHASE_OTHER, s, [&] { return launch_noise(na, s); }));
+}
+
+pm_status nspt_steps(void* U, int R, const nspt_params* p, unsigned long long seed, unsigned long long step0,
+                     int nsteps, int prec, void* workspace, size_t workspace_bytes, hipStream_t s) {
+  if (!valid_params(R, p, prec)) return PM_ERR_INVALID;
+  if (!U || !workspace || nsteps < 1 || nsteps > kMaxMdSteps) return PM_ERR_INVALID;
+  if (reinterpret_cast<uintptr_t>(U) % 16 || reinterpret_cast<uintptr_t>(workspace) % kAlign) return PM_ERR_INVALID;
+  const Layout l = layout(R, p, prec);
+  if (workspace_bytes < l.total) return PM_ERR_WORKSPACE;
+  const size_t ub = static_cast<size_t>(R) * 4 * l.nord * l.E * 16;
+  if (overlaps(workspace, l.total, U, ub)) return PM_ERR_INVALID;
+  double2* eta = reinterpret_cast<double2*>(static_cast<char*>(workspace) + l.eta);
+  Run run(U, R, p, prec, workspace, s);
+  pm_status e = PM_OK;
+  for (int t = 0; t < nsteps && !e; ++t) {
+    e = nspt_noise(eta, R, p->n, seed, step0 + static_cast<unsigned long long>(t), s);
+    if (!e) e = run.links_forward();
+    if (!e) e = run.staples();
+    if (!e) e = run.force(eta, nullptr, 0.0, 0.0, true);
+    if (!e) e = run.exp_and_update();
+  }
   return e;
 }
 

@@ -108,6 +108,18 @@ hipError_t launch_inv_combine(const CombineArgs& a, int L, int max_entries, Four
 hipError_t launch_trace(const TraceArgs& a, int max_nord, hipStream_t s);
 hipError_t launch_force(const ForceArgs& a, int n, int max_nord, hipStream_t s);
 hipError_t launch_refresh(const RefreshArgs& a, hipStream_t s);
+
+// Counter-based Langevin noise: `count` Hermitian traceless n x n matrices
+// (matrix m = 4 r + mu) of step `step` under `seed` (Philox4x64-10 and
+// Box-Muller; the mapping is documented with nspt_noise in polymat.h).
+struct NoiseArgs {
+  double2* eta;            // [count][n][n]
+  unsigned long long seed;
+  unsigned long long step;
+  int n;
+  int count;
+};
+hipError_t launch_noise(const NoiseArgs& a, hipStream_t s);
 hipError_t launch_action(const ActionArgs& a, hipStream_t s);
 hipError_t launch_series_scale(const SeriesScaleArgs& a, int max_nord, hipStream_t s);
 

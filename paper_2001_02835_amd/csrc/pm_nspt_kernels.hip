@@ -121,6 +121,79 @@ __global__ __launch_bounds__(kFftThreads, fft_min_waves<L>()) void k_inv_combine
       if (k >= jb.kmin) jb.dst[static_cast<size_t>(k) * E + e] = cscale(acc[k][el], jb.rec->sinv[k]);
 }
 
+// ------------------------------------------------------------------ noise
+
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) on the counter c under
+// the key (k0, k1): ten rounds of two 64 x 64 -> 128-bit products and a Weyl
+// key schedule.
+__device__ __forceinline__ void philox4x64_10(unsigned long long (&c)[4], unsigned long long k0,
+                                              unsigned long long k1) {
+  constexpr unsigned long long kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
+  constexpr unsigned long long kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const unsigned long long hi0 = __umul64hi(kM0, c[0]), lo0 = kM0 * c[0];
+    const unsigned long long hi1 = __umul64hi(kM1, c[2]), lo1 = kM1 * c[2];
+    const unsigned long long n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += kW0;
+    k1 += kW1;
+  }
+}
+
+// Entry pairs i <= j of matrix blockIdx.y: counter (i n + j, m, step, 0),
+// key (seed, 0); u_a = ((x0 >> 11) + 1) 2^-53, u_b = (x1 >> 11) 2^-53,
+// Box-Muller z0 = rho cos(2 pi u_b), z1 = rho sin(2 pi u_b), rho = sqrt(-2 ln u_a);
+// eta_ij = (z0 + i z1) / sqrt 2 = conj(eta_ji) for i < j, eta_ii = z0.
+__global__ __launch_bounds__(256) void k_noise(NoiseArgs a) {
+  const int m = blockIdx.y;
+  const int n = a.n;
+  const size_t E = static_cast<size_t>(n) * n;
+  double2* eta = a.eta + static_cast<size_t>(m) * E;
+  const double r2 = sqrt(2.0);
+  for (size_t e = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; e < E;
+       e += static_cast<size_t>(gridDim.x) * 256) {
+    const int i = static_cast<int>(e / n), j = static_cast<int>(e - static_cast<size_t>(i) * n);
+    if (i > j) continue;
+    unsigned long long c[4] = {static_cast<unsigned long long>(e), static_cast<unsigned long long>(m), a.step, 0ull};
+    philox4x64_10(c, a.seed, 0ull);
+    const double ua = static_cast<double>((c[0] >> 11) + 1ull) * 0x1.0p-53;
+    const double ub = static_cast<double>(c[1] >> 11) * 0x1.0p-53;
+    const double rho = sqrt(-2.0 * log(ua));
+    const double ang = 2.0 * M_PI * ub;
+    const double z0 = rho * cos(ang), z1 = rho * sin(ang);
+    if (i == j) {
+      eta[e] = make_double2(z0, 0.0);
+    } else {
+      const double re = z0 / r2, im = z1 / r2;
+      eta[e] = make_double2(re, im);
+      eta[static_cast<size_t>(j) * n + i] = make_double2(re, -im);
+    }
+  }
+}
+
+// eta_ii -= Tr(eta) / n for matrix blockIdx.x (the diagonal is real); the
+// trace is summed in a fixed order (strided partial sums, then a tree).
+__global__ __launch_bounds__(256) void k_noise_trace(NoiseArgs a) {
+  __shared__ double part[256];
+  const int n = a.n;
+  const size_t E = static_cast<size_t>(n) * n;
+  double2* eta = a.eta + static_cast<size_t>(blockIdx.x) * E;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += eta[static_cast<size_t>(i) * (n + 1)].x;
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (static_cast<int>(threadIdx.x) < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double tr = part[0] / n;
+  for (int i = threadIdx.x; i < n; i += 256) eta[static_cast<size_t>(i) * (n + 1)].x -= tr;
+}
+
 // ---------------------------------------------------------------- refresh
 
 // P^(1) = eta, every other order zero (grid-stride over the series).
@@ -284,6 +357,17 @@ hipError_t launch_inv_combine(const CombineArgs& a, int L, int max_entries, Four
   if (ns == 6) return fin == kF64 ? combine_dispatch<kF64, 6>(a, L, g, s) : combine_dispatch<kF32, 6>(a, L, g, s);
   if (ns == 8) return fin == kF64 ? combine_dispatch<kF64, 8>(a, L, g, s) : combine_dispatch<kF32, 8>(a, L, g, s);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_noise(const NoiseArgs& a, hipStream_t s) {
+  if (a.count <= 0 || a.n <= 0) return hipSuccess;
+  const size_t E = static_cast<size_t>(a.n) * a.n;
+  const unsigned gx = static_cast<unsigned>(std::min<size_t>((E + 255) / 256, 1024));
+  k_noise<<<dim3(gx, a.count), 256, 0, s>>>(a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_noise_trace<<<a.count, 256, 0, s>>>(a);
+  return hipGetLastError();
 }
 
 hipError_t launch_refresh(const RefreshArgs& a, hipStream_t s) {

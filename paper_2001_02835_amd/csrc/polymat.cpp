@@ -573,6 +573,18 @@ pm_status nspt_wilson_loop(const void* U, int replicas, const nspt_params* param
                          static_cast<hipStream_t>(stream));
 }
 
+pm_status nspt_noise(void* eta, int replicas, int n, unsigned long long seed, unsigned long long step,
+                     void* stream) {
+  return pm::nspt_noise(eta, replicas, n, seed, step, static_cast<hipStream_t>(stream));
+}
+
+pm_status nspt_langevin_steps(void* U, int replicas, const nspt_params* params, unsigned long long seed,
+                              unsigned long long step0, int nsteps, int precision, void* workspace,
+                              size_t workspace_bytes, void* stream) {
+  return pm::nspt_steps(U, replicas, params, seed, step0, nsteps, precision, workspace, workspace_bytes,
+                        static_cast<hipStream_t>(stream));
+}
+
 pm_status nspt_gauge_fix(void* U, int replicas, const nspt_params* params, double alpha, int precision,
                          void* workspace, size_t workspace_bytes, void* stream) {
   return pm::nspt_gauge(U, replicas, params, alpha, precision, workspace, workspace_bytes,

@@ -221,3 +221,24 @@ def test_limits_of_counts_and_sizes():
     arr[0].n, arr[0].ntrunc = 9, 7
     assert lib.polymat_batched_workspace_size(arr, 4097, 0) == 0
     assert lib.polymat_mul_batched(arr, 4097, 0, FAKE_WS, 1 << 40, None) == nat.PM_ERR_INVALID
+
+
+def test_noise_and_steps_reject_bad_arguments():
+    lib = pm.lib()
+    E = nat.PM_ERR_INVALID
+    assert lib.nspt_noise(None, 1, 9, 1, 0, None) == E
+    assert lib.nspt_noise(FAKE_A, 0, 9, 1, 0, None) == E
+    assert lib.nspt_noise(FAKE_A, 1025, 9, 1, 0, None) == E
+    assert lib.nspt_noise(FAKE_A, 1, 0, 1, 0, None) == E
+    assert lib.nspt_noise(FAKE_A, 1, 4097, 1, 0, None) == E
+    assert lib.nspt_noise(FAKE_A + 8, 1, 9, 1, 0, None) == E                        # misaligned
+    good = nat.NsptParams(9, 3, 1, 7, 0.01)
+    need = lib.nspt_workspace_size(1, ctypes.byref(good), 0)
+    f = lambda U=FAKE_A, prm=good, ns=2, nb=need: lib.nspt_langevin_steps(U, 1, ctypes.byref(prm), 5, 0, ns, 0,
+                                                                          FAKE_WS, nb, None)
+    assert f(ns=0) == E
+    assert f(ns=100001) == E
+    assert f(U=None) == E
+    assert f(U=FAKE_WS) == E                                                        # U overlaps the workspace
+    assert f(nb=need - 1) == nat.PM_ERR_WORKSPACE
+    assert f(prm=nat.NsptParams(9, 3, 1, 7, 0.0)) == E
