@@ -124,8 +124,8 @@ def bench_uneven(torch, synth, pm, dev, steps):
 def bench_nspt(torch, synth, pm, dev, steps):
     """NSPT Euler-Langevin step: 8 replicas x 4 links, SU(225) (L=15, k=4), ntrunc=31,
     eps=0.01, started at the twisted vacuum and evolved by warm-up steps; the same
-    step replayed from a captured HIP graph; then one stochastic gauge-fixing step
-    (alpha = 0.1) on the same links."""
+    step replayed from a captured HIP graph; steps with the noise drawn on the
+    device; then one stochastic gauge-fixing step (alpha = 0.1) on the same links."""
     import numpy as np
     L, k, nt, eps, R = 15, 4, 31, 0.01, 8
     n = L * L
@@ -177,6 +177,12 @@ def bench_nspt(torch, synth, pm, dev, steps):
             del graph
         except Exception as exc:   # report, do not fail the bench line
             graph_ms = f"capture failed: {exc}"
+        # the same number of steps in one call with the noise drawn on the device
+        e0.record()
+        pm.nspt_langevin_steps(u, prm, 2024, 0, steps, prec, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        dev_noise_ms = round(e0.elapsed_time(e1) / steps, 3)
         # one stochastic gauge-fixing step (alpha = 0.1) on the evolved links
         pm.nspt_gauge_fix(u, prm, 0.1, prec, ws=ws)
         torch.cuda.synchronize()
@@ -189,7 +195,8 @@ def bench_nspt(torch, synth, pm, dev, steps):
         res[prec] = {"ms_per_step": round(ms, 3), "steps_per_s": round(1e3 / ms, 3),
                      "replica_steps_per_s": round(R * 1e3 / ms, 2),
                      "phase_ms_per_step": {kk: round(v[0] / steps, 3) for kk, v in ph.items() if v[1]},
-                     "graph_ms_per_step": graph_ms, "gauge_fix_ms": round(gms, 3)}
+                     "graph_ms_per_step": graph_ms, "device_noise_ms_per_step": dev_noise_ms,
+                     "gauge_fix_ms": round(gms, 3)}
         del ws
     return res
 
