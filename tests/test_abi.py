@@ -242,3 +242,17 @@ def test_noise_and_steps_reject_bad_arguments():
     assert f(U=FAKE_WS) == E                                                        # U overlaps the workspace
     assert f(nb=need - 1) == nat.PM_ERR_WORKSPACE
     assert f(prm=nat.NsptParams(9, 3, 1, 7, 0.0)) == E
+
+
+@pytest.mark.parametrize("lang,std", [("c", "-std=c99"), ("c++", "-std=c++11")])
+def test_header_is_plain_c_and_cxx(lang, std):
+    """include/polymat.h needs no HIP or torch headers: it compiles as C99
+    and as C++11 with warnings as errors."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc" if lang == "c" else "g++")
+    if cc is None:
+        pytest.skip("no host compiler")
+    r = subprocess.run([cc, std, "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only", "-x", lang, HEADER],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
