@@ -1,8 +1,9 @@
 /*
  * polymat.h - C ABI of the MI355X FFT-CONV library for truncated matrix power
- * series and the NSPT updates (Euler-Langevin step, leapfrog molecular-
- * dynamics trajectory) and action series of the twisted Eguchi-Kawai model
- * (arXiv:2001.02835).
+ * series and the NSPT updates of the twisted Eguchi-Kawai model
+ * (arXiv:2001.02835): the Euler-Langevin step (with caller-supplied noise or
+ * noise drawn on the device), the leapfrog molecular-dynamics trajectory, a
+ * stochastic gauge-fixing step, and the action and Wilson-loop series.
  *
  * Series layout (all entry points): a truncated power series in g whose
  * coefficients are N x N complex matrices (Section 2, eq. (4)) is a dense,
@@ -22,8 +23,8 @@
  * caller's synchronisation.  No C++ exception crosses this interface.
  * Calls enqueue kernel launches only (no memset or copy), so a call can be
  * captured into a HIP graph and replayed (with phase timing off).
- * Host-side state (none beyond constants) is thread-safe; calls that share
- * one workspace must be ordered on one stream.
+ * Host-side state (phase-timing records; otherwise constants) is
+ * thread-safe; calls that share one workspace must be ordered on one stream.
  *
  * Precision modes (the per-frequency products only; the transforms, their
  * twiddles and 1/L normalisation, the rescaling and every value stored in a
