@@ -204,7 +204,9 @@ def bench_nspt(torch, synth, pm, dev, steps):
 def bench_md(torch, synth, pm, dev, nsteps):
     """NSPT molecular-dynamics trajectory (leapfrog, momentum refresh): 8 replicas
     x 4 links, SU(225) (L=15, k=4), ntrunc=31, dt=0.05, started at the twisted
-    vacuum and evolved by one warm-up trajectory."""
+    vacuum and evolved by a short warm-up trajectory; one timed trajectory of
+    `nsteps` MD steps (the paper's unit is a trajectory of 40 MD steps), then
+    one more with HIP events around every launch for the phase times."""
     L, k, nt, dt, R = 15, 4, 31, 0.05, 8
     n = L * L
     u = torch.from_numpy(synth.vacuum_links(L, k, nt, replicas=R)).to(dev)
@@ -216,7 +218,7 @@ def bench_md(torch, synth, pm, dev, nsteps):
                        f"{nsteps} MD steps per trajectory with momentum refresh, FP64 links"}
     for prec in ("fp64", "bf16x3"):
         ws = pm.workspace(pm.nspt_workspace_size(R, prm, prec), dev)
-        pm.nspt_md_trajectory(u, P, prm, nsteps, eta=noise[0], precision=prec, ws=ws)
+        pm.nspt_md_trajectory(u, P, prm, min(nsteps, 2), eta=noise[0], precision=prec, ws=ws)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -236,7 +238,8 @@ def bench_md(torch, synth, pm, dev, nsteps):
                      "force_evaluations": nsteps + 1,
                      "phase_ms_per_trajectory": {kk: round(v[0], 3) for kk, v in ph.items() if v[1]},
                      "paper_run_estimate_s": {"trajectories": 10, "md_steps": 40,
-                                              "seconds": round(10 * 40 * ms / nsteps / 1e3, 2)}}
+                                              "seconds": round(10 * 40 * ms / nsteps / 1e3, 2),
+                                              "from": f"one measured trajectory of {nsteps} MD steps"}}
         del ws
     return res
 
@@ -272,9 +275,33 @@ def bench_crossover(torch, synth, pm, dev, reps=20):
     return res
 
 
-def cpu_baseline(seconds: float):
+def cpu_fftconv(a, b, workers):
+    """FFT-CONV on the host CPU, the analogue of the paper's CPU FFT-CONV
+    (its Section 3 comparison): order-axis FFTs of the zero-padded operands
+    with scipy.fft over `workers` threads, one complex128 matrix product per
+    frequency (BLAS), the inverse FFT, truncation.  A timing baseline only:
+    nothing on the GPU path uses it."""
+    import numpy as np
+    import scipy.fft as sfft
+    nt1 = a.shape[0]
+    L = 4
+    while L < 2 * nt1:
+        L *= 2
+    at = sfft.fft(a, n=L, axis=0, workers=workers)
+    bt = sfft.fft(b, n=L, axis=0, workers=workers)
+    ct = np.empty_like(at)
+    for p in range(L):
+        np.matmul(at[p], bt[p], out=ct[p])
+    return sfft.ifft(ct, axis=0, workers=workers)[:nt1]
+
+
+def cpu_baseline(seconds: float, gpu_c2=None, gpu_c3=None):
     """The FP64 oracle (naive star product, BLAS matmul per term) on the host
-    cores, on products of the headline shape until `seconds` have elapsed."""
+    cores, on the four headline products (the same seeded inputs as the GPU
+    step) in turn until `seconds` have elapsed; beside it the CPU FFT-CONV
+    baseline on the same products.  The oracle's first result of each product
+    (and one oracle product of the ntrunc = 63 workload) also gives the
+    per-order error of the GPU results passed in."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
@@ -282,22 +309,65 @@ def cpu_baseline(seconds: float):
     from oracle import series as ser
 
     n, nt = 225, 31
-    a = synth.random_series(synth.rng_for(2, 0, 0), n, nt, 0.5)
-    b = synth.random_series(synth.rng_for(2, 0, 1), n, nt, 0.5)
-    ser.star(a[:2], b[:2])                           # warm the BLAS pool
+    ops = [(synth.random_series(synth.rng_for(2, i, 0), n, nt, 0.5),
+            synth.random_series(synth.rng_for(2, i, 1), n, nt, 0.5)) for i in range(4)]
+    ser.star(ops[0][0][:2], ops[0][1][:2])            # warm the BLAS pool
+    refs = [None] * 4
     done, t0 = 0, time.perf_counter()
     while True:
-        ser.star(a, b)
+        i = done % 4
+        c = ser.star(*ops[i])
+        if refs[i] is None:
+            refs[i] = c
         done += 1
         el = time.perf_counter() - t0
-        if el >= seconds:
+        if el >= seconds and done >= 4:
             break
     threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
-    return {
+    ncpu = os.cpu_count() or 1
+    out = {
         "value": done / el, "unit": "mults/s", "cores": int(threads), "kind": "oracle",
-        "sample": f"{done} products N=225 ntrunc=31 (entries N(0,1)*0.5^k), naive O(ntrunc^2) star product "
-                  f"with numpy complex128 matmul, {el:.1f} s on {os.cpu_count()} host CPUs",
+        "sample": f"{done} products N=225 ntrunc=31 (the four headline products in turn, entries N(0,1)*0.5^k), "
+                  f"naive O(ntrunc^2) star product with numpy complex128 matmul, {el:.1f} s on {ncpu} host CPUs",
     }
+    # the paper-analog CPU FFT-CONV on the same products
+    cpu_fftconv(*ops[0], ncpu)
+    fdone, t0 = 0, time.perf_counter()
+    ferr = 0.0
+    while True:
+        i = fdone % 4
+        c = cpu_fftconv(*ops[i], ncpu)
+        if fdone < 4:
+            ferr = max(ferr, float(order_errors(c, refs[i]).max()))
+        fdone += 1
+        fel = time.perf_counter() - t0
+        if fel >= seconds / 4 and fdone >= 4:
+            break
+    out["fftconv"] = {"value": round(fdone / fel, 2), "unit": "mults/s", "threads": ncpu,
+                      "kind": "CPU FFT-CONV (scipy.fft workers + per-frequency BLAS matmul), not tuned",
+                      "sample": f"{fdone} products N=225 ntrunc=31 in {fel:.1f} s",
+                      "max_per_order_error_vs_oracle": float(f"{ferr:.3e}")}
+    errs = {}
+    if gpu_c2 is not None:
+        e = np.stack([order_errors(gpu_c2[i], refs[i]) for i in range(4)])
+        errs["n225_nt31_x4_fp64"] = {"max": float(f"{e.max():.3e}"), "order_of_max": int(e.max(axis=0).argmax())}
+    if gpu_c3:
+        a3 = synth.random_series(synth.rng_for(3, 0, 0), 225, 63, 1.3)
+        b3 = synth.random_series(synth.rng_for(3, 0, 1), 225, 63, 1.3)
+        ref3 = ser.star(a3, b3)
+        for prec, c in gpu_c3.items():
+            e = order_errors(c, ref3)
+            errs[f"n225_nt63_{prec}"] = {"max": float(f"{e.max():.3e}"), "order_of_max": int(e.argmax()),
+                                         "median": float(f"{np.median(e):.3e}")}
+    return out, errs
+
+
+def order_errors(c, ref):
+    """e_k = ||C^(k) - C_ref^(k)||_F / ||C_ref^(k)||_F for every order k."""
+    import numpy as np
+    num = np.sqrt(np.sum(np.abs(c - ref) ** 2, axis=(-2, -1)))
+    den = np.sqrt(np.sum(np.abs(ref) ** 2, axis=(-2, -1)))
+    return num / np.where(den > 0, den, 1.0)
 
 
 def main(argv=None):
@@ -311,7 +381,7 @@ def main(argv=None):
     ap.add_argument("--precision-only", action="store_true",
                     help="of the extra lines, run only the ntrunc = 63 precision comparison")
     ap.add_argument("--nspt-steps", type=int, default=3)
-    ap.add_argument("--md-steps", type=int, default=4, help="leapfrog steps of the timed MD trajectory")
+    ap.add_argument("--md-steps", type=int, default=40, help="leapfrog steps of the timed MD trajectory")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args(argv)
@@ -353,10 +423,18 @@ def main(argv=None):
     work = f"{count} products x {L} modes x 8*{n}^3 flop = {flops_step/1e9:.2f} GFLOP per launch"
     achieved = flops_step * args.steps / (pms * 1e-3) / 1e12
     traffic = load_traffic("k_cgemm_f64_c2")
+    # matrix-core flops issued per useful flop: the three-product complex form
+    # issues 3 real products where the useful count has 4
+    issued_ratio = 1.0 if os.environ.get("POLYMAT_GEMM_4M") == "1" else 0.75
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK["fp64"], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK["fp64"], 4), "traffic": traffic, "kernel": kernel,
                 "algorithmic_work": work, "avg_launch_ms": round(pms / max(plaunch, 1), 4),
-                "launches_per_step": plaunch // args.steps}
+                "launches_per_step": plaunch // args.steps,
+                "issued_achieved": round(achieved * issued_ratio, 2),
+                "issued_frac": round(achieved * issued_ratio / PEAK["fp64"], 4),
+                "issued_note": "MFMA flops actually issued: 6 N^3 per mode (3-product complex form) "
+                               "against the 8 N^3 useful count"}
+    gpu_c2 = [it["C"].cpu().numpy() for it in items]
     phase_ms = {k: round(v[0] / args.steps, 4) for k, v in phases.items() if v[1]}
 
     out = {
@@ -374,6 +452,7 @@ def main(argv=None):
     }
 
     # ---- ntrunc = 63: FP64 vs FP32 vs split-BF16 on the same GPU
+    gpu_c3 = {}
     if not args.no_extra:
         n3, nt3 = 225, 63
         items3 = make_inputs(torch, synth, 3, 1, n3, nt3, 1.3, dev)
@@ -383,6 +462,7 @@ def main(argv=None):
                 ws3 = pm.workspace(pm.batched_workspace_size(items3, prec), dev)
                 st3 = max(args.steps // 4, 10)
                 ms3, ph3 = time_steps(torch, pm, items3, prec, st3, 3, ws3, timing=True)
+                gpu_c3[prec] = items3[0]["C"].cpu().numpy()
                 pms3, pl3 = ph3["product"]
                 fl3 = pm.transform_length(nt3) * 8.0 * n3 ** 3
                 ach = fl3 / (pms3 * 1e-3 / max(pl3, 1)) / 1e12
@@ -410,7 +490,9 @@ def main(argv=None):
         out["naive_vs_fftconv"] = bench_crossover(torch, synth, pm, dev)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        out["cpu_baseline"], out["per_order_error"] = cpu_baseline(args.cpu_seconds, gpu_c2, gpu_c3)
+        out["per_order_error"]["metric"] = ("max over orders k of ||C_k - C_k^oracle||_F / ||C_k^oracle||_F, "
+                                            "GPU results of the timed workloads against the FP64 oracle")
     out["context"] = ("paper: GPU FFT-CONV 9x faster than CPU FFT-CONV for the whole NSPT run at SU(225), "
                       "O(g^31), on 4xP100 vs 2xXeon 6154 (no absolute product rate published)")
     print(json.dumps(out))

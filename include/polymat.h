@@ -59,7 +59,10 @@ enum {
   PM_ERR_INVALID = 1,     /* bad size, null/misaligned pointer, overlap, bad scale */
   PM_ERR_WORKSPACE = 2,   /* workspace smaller than the *_size query requires */
   PM_ERR_DEVICE = 3,      /* a HIP call failed (launch error or earlier fault) */
-  PM_ERR_UNSUPPORTED = 4  /* valid request outside what is built (e.g. ntrunc > 63) */
+  PM_ERR_UNSUPPORTED = 4, /* valid request outside what is built (e.g. ntrunc > 63) */
+  PM_ERR_NONFINITE = 5    /* finiteness check on (polymat_check_enable): a NaN or
+                             Inf in an operand, or a result coefficient that is
+                             not finite */
 };
 typedef int pm_status;
 
@@ -165,6 +168,23 @@ size_t polymat_batched_workspace_size(const pm_problem* problems, int count,
 pm_status polymat_mul_batched(const pm_problem* problems, int count,
                               int precision, void* workspace,
                               size_t workspace_bytes, void* stream);
+
+/*
+ * polymat_check_enable - opt-in finiteness check of polymat_mul and
+ * polymat_mul_batched (process-wide, off by default).  The check itself runs
+ * on the device in every call: the rescaling step records whether a
+ * per-order norm of an operand is not finite (auto scale only), and the
+ * inverse transform (Steps 4-5) records whether it stored a non-finite
+ * coefficient of C; both words sit in the product's region of the workspace.
+ * A NaN or Inf anywhere in A or B reaches every coefficient of C through the
+ * order-axis transform, so the second word also covers a fixed scale.
+ * With the check on, a call enqueues its kernels, then synchronises `stream`,
+ * reads those words back and returns PM_ERR_NONFINITE if any is set (C is
+ * written all the same); polymat_mul then always takes the transform path.
+ * A call on a stream under graph capture returns PM_ERR_INVALID while the
+ * check is on.  The NSPT entry points are not checked.
+ */
+pm_status polymat_check_enable(int on);
 
 /*
  * polymat_forward_transform - Steps 1-2 alone (eqs. (6)-(7)), FP64:

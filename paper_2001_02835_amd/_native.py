@@ -11,7 +11,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpolymat.so")
 
-PM_OK, PM_ERR_INVALID, PM_ERR_WORKSPACE, PM_ERR_DEVICE, PM_ERR_UNSUPPORTED = range(5)
+PM_OK, PM_ERR_INVALID, PM_ERR_WORKSPACE, PM_ERR_DEVICE, PM_ERR_UNSUPPORTED, PM_ERR_NONFINITE = range(6)
 PM_PREC_FP64, PM_PREC_FP32, PM_PREC_BF16X3 = range(3)
 PM_OP_N, PM_OP_C = 0, 1
 PM_MAX_NTRUNC = 63
@@ -56,6 +56,7 @@ SIGNATURES = {
     "polymat_inverse_transform": (_I, [_VP, _VP, _I, _I, _D, _VP, _SZ, _VP]),
     "polymat_transform_workspace_size": (_SZ, []),
     "polymat_timing_enable": (_I, [_I]),
+    "polymat_check_enable": (_I, [_I]),
     "polymat_timing_read": (_I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
     "nspt_workspace_size": (_SZ, [_I, ctypes.POINTER(NsptParams), _I]),
     "nspt_langevin_step": (_I, [_VP, _VP, _I, ctypes.POINTER(NsptParams), _I, _VP, _SZ, _VP]),

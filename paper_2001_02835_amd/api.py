@@ -285,6 +285,13 @@ def nspt_wilson_loop(U: torch.Tensor, params: nat.NsptParams, a: int, b: int, pr
     return W
 
 
+def check_enable(on: bool = True) -> None:
+    """Turn the finiteness check of polymat_mul / polymat_mul_batched on or off:
+    while on, those calls synchronise the stream and raise PolymatError with
+    status PM_ERR_NONFINITE when an operand or a result coefficient is not finite."""
+    nat.check(nat.lib().polymat_check_enable(1 if on else 0), "polymat_check_enable")
+
+
 def timing_enable(on: bool = True) -> None:
     """Bracket every library launch with HIP events (for measurement only)."""
     nat.check(nat.lib().polymat_timing_enable(1 if on else 0), "polymat_timing_enable")

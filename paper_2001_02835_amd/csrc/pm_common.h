@@ -147,10 +147,15 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 // ------------------------------------------------------------- job tables
 
 // Scale record of one product (device memory, written by the scale kernel):
-//   s, then spow[k] = s^k (k < kMaxL/2), then sinv[k] = s^-k / L.
+//   s, two status words, then spow[k] = s^k (k < kMaxL/2), then
+//   sinv[k] = s^-k / L.  in_bad is set by the scale kernel when a per-order
+//   norm of an operand is not finite (a NaN or Inf input, or |x|^2 beyond the
+//   FP64 range); out_bad is cleared by the scale kernel and set by the
+//   inverse transform when it stores a non-finite coefficient.
 struct ScaleRec {
   double s;
-  double pad_;
+  unsigned int in_bad;
+  unsigned int out_bad;
   double spow[kMaxL / 2];
   double sinv[kMaxL / 2];
 };

@@ -26,7 +26,7 @@ struct FwdJob {
 struct InvJob {
   const void* src;         // [L][E] double2 or float2
   double2* dst;            // [nord][E] complex128
-  const ScaleRec* rec;     // s^-k / L table
+  ScaleRec* rec;           // s^-k / L table; out_bad is set on a non-finite store
   int E;
   int nord;
 };

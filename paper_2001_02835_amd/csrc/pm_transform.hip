@@ -70,9 +70,16 @@ __global__ __launch_bounds__(kFftThreads, (inverse_min_waves<L, FT>())) void k_i
   auto load = [&](int p) { return valid ? load_mode<FT>(jb.src, jb.E, p, e) : make_double2(0.0, 0.0); };
   inverse_to_lds<L>(load, acc, lane, r);
   // Steps 4-5: 1/L, unscale by s^-k (one table), keep orders < nord
-  if (valid)
-    for (int k = threadIdx.x / ENT; k < jb.nord; k += KSTEP)
-      jb.dst[static_cast<size_t>(k) * jb.E + e] = cscale(acc[k][el], jb.rec->sinv[k]);
+  if (valid) {
+    bool bad = false;
+    for (int k = threadIdx.x / ENT; k < jb.nord; k += KSTEP) {
+      const double2 v = cscale(acc[k][el], jb.rec->sinv[k]);
+      bad = bad || !isfinite(v.x) || !isfinite(v.y);
+      jb.dst[static_cast<size_t>(k) * jb.E + e] = v;
+    }
+    // every writer stores the same value; the scale kernel cleared it
+    if (bad) jb.rec->out_bad = 1u;
+  }
 }
 
 // ------------------------------------------------------------ norms / scale
@@ -126,6 +133,7 @@ __global__ __launch_bounds__(64) void k_scale(ScaleArgs args) {
   const int nord = jb.nord;
   const int tid = threadIdx.x;
   double t = 0.0;
+  bool in_bad = false;
   if (jb.fixed_s > 0.0) {
     t = log(jb.fixed_s);
   } else if (nord > 1) {
@@ -147,6 +155,7 @@ __global__ __launch_bounds__(64) void k_scale(ScaleArgs args) {
       na = sqrt((sa[0] + sa[1]) + (sa[2] + sa[3]));
       nb = sqrt((sb[0] + sb[1]) + (sb[2] + sb[3]));
     }
+    in_bad = __any(!isfinite(na) || !isfinite(nb));
     // orders below 1e-15 of an operand's largest one carry no information in
     // FP64 (e.g. the rounding residue of a product at orders that vanish
     // exactly); they are left out so that s is not chosen to lift them
@@ -228,7 +237,11 @@ __global__ __launch_bounds__(64) void k_scale(ScaleArgs args) {
     }
   }
   ScaleRec* rec = jb.rec;
-  if (tid == 0) rec->s = exp(t);
+  if (tid == 0) {
+    rec->s = exp(t);
+    rec->in_bad = in_bad ? 1u : 0u;
+    rec->out_bad = 0u;
+  }
   rec->spow[tid] = exp(t * tid);
   rec->sinv[tid] = exp(-t * tid) / jb.L;
 }

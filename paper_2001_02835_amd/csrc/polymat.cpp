@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <cstddef>
 #include <cstring>
 #include <atomic>
 #include <map>
@@ -102,6 +103,14 @@ pm_status check_problem_shape(const void* A, const void* B, const void* C, int n
 }
 
 pm_status from_hip(hipError_t e) { return e == hipSuccess ? PM_OK : PM_ERR_DEVICE; }
+
+// Finiteness check of the product entry points (polymat_check_enable).
+std::atomic<bool> g_check{false};
+
+bool stream_capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
 
 // ------------------------------------------------------------ phase timing
 
@@ -263,7 +272,7 @@ pm_status enqueue_products(const std::vector<Planned>& items, int prec, hipStrea
       InvJob& j = ia.jobs[ia.njobs++];
       j.src = it->ws + it->lay.Ct;
       j.dst = static_cast<double2*>(it->pr.C);
-      j.rec = reinterpret_cast<const ScaleRec*>(it->ws + it->lay.rec);
+      j.rec = reinterpret_cast<ScaleRec*>(it->ws + it->lay.rec);
       j.E = it->pr.n * it->pr.n;
       j.nord = it->pr.ntrunc + 1;
       maxE = std::max(maxE, j.E);
@@ -339,6 +348,11 @@ extern "C" {
 
 int polymat_abi_version(void) { return 1; }
 
+pm_status polymat_check_enable(int on) {
+  g_check.store(on != 0);
+  return PM_OK;
+}
+
 pm_status polymat_timing_enable(int on) {
   g_timing.store(on != 0);
   return PM_OK;
@@ -383,6 +397,7 @@ const char* polymat_strerror(pm_status status) {
     case PM_ERR_WORKSPACE: return "workspace too small";
     case PM_ERR_DEVICE: return "HIP device error";
     case PM_ERR_UNSUPPORTED: return "unsupported size or mode";
+    case PM_ERR_NONFINITE: return "non-finite value in an operand or the result";
     default: return "unknown status";
   }
 }
@@ -417,7 +432,20 @@ pm_status polymat_mul_batched(const pm_problem* problems, int count, int precisi
   std::sort(outs.begin(), outs.end(), [](const Range& a, const Range& b) { return a.b < b.b; });
   for (size_t i = 1; i < outs.size(); ++i)
     if (outs[i].b < outs[i - 1].e) return PM_ERR_INVALID;
-  return enqueue_products(items, precision, static_cast<hipStream_t>(stream));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool check = g_check.load(std::memory_order_relaxed);
+  if (check && stream_capturing(st)) return PM_ERR_INVALID;
+  s = enqueue_products(items, precision, st);
+  if (s || !check) return s;
+  // read back the status words of every product's scale record
+  if (hipStreamSynchronize(st) != hipSuccess) return PM_ERR_DEVICE;
+  for (const Planned& it : items) {
+    unsigned int flags[2] = {0u, 0u};
+    const char* rec = it.ws + it.lay.rec + offsetof(ScaleRec, in_bad);
+    if (hipMemcpy(flags, rec, sizeof(flags), hipMemcpyDeviceToHost) != hipSuccess) return PM_ERR_DEVICE;
+    if (flags[0] || flags[1]) return PM_ERR_NONFINITE;
+  }
+  return PM_OK;
 }
 
 pm_status polymat_mul_naive(const void* A, const void* B, void* C, int n, int ntrunc, int op_a, int op_b,
@@ -452,7 +480,7 @@ pm_status polymat_mul(const void* A, const void* B, void* C, int n, int ntrunc, 
   // form of eq. (5): one N x N product instead of L = 4 mode products plus the
   // transforms.  The arguments are validated as for the transform path.
   if (precision == PM_PREC_FP64 && ntrunc >= 0 && ntrunc <= kNaiveMaxNtrunc && n >= 1 && n <= PM_MAX_N && A &&
-      B && C) {
+      B && C && !g_check.load(std::memory_order_relaxed)) {
     const size_t sb = series_bytes(n, ntrunc);
     if (!overlaps(range_of(C, sb), range_of(A, sb)) && !overlaps(range_of(C, sb), range_of(B, sb))) {
       if (!std::isfinite(scale) || scale < 0.0) return PM_ERR_INVALID;
@@ -545,7 +573,7 @@ pm_status polymat_inverse_transform(const void* Ct, void* C, int n, int ntrunc, 
   ia.njobs = 1;
   ia.jobs[0].src = Ct;
   ia.jobs[0].dst = static_cast<double2*>(C);
-  ia.jobs[0].rec = static_cast<const ScaleRec*>(workspace);
+  ia.jobs[0].rec = static_cast<ScaleRec*>(workspace);
   ia.jobs[0].E = n * n;
   ia.jobs[0].nord = ntrunc + 1;
   return from_hip(launch_inverse(ia, L, n * n, kF64, st));

@@ -39,9 +39,19 @@ def test_library_loads_and_exports_every_declared_function():
 
 
 def test_strerror_texts():
-    for s in range(5):
+    for s in range(6):
         assert isinstance(nat.strerror(s), str) and nat.strerror(s)
     assert nat.strerror(99) == "unknown status"
+
+
+def test_check_mode_switches_and_nonfinite_status_has_text():
+    lib = pm.lib()
+    assert nat.PM_ERR_NONFINITE == 5
+    assert "finite" in nat.strerror(nat.PM_ERR_NONFINITE)
+    assert lib.polymat_check_enable(1) == nat.PM_OK
+    # validation still happens first: an invalid call returns before any check
+    assert lib.polymat_mul(None, FAKE_B, FAKE_C, 9, 7, 0, 0.0, FAKE_WS, 1 << 30, None) == nat.PM_ERR_INVALID
+    assert lib.polymat_check_enable(0) == nat.PM_OK
 
 
 def test_transform_length():

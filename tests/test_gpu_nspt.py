@@ -100,16 +100,3 @@ def test_step_precisions(prec):
     worst = max(order_errors(got[0, mu], ref[0, mu]).max() for mu in range(4))
     print(f"{prec}: worst per-order error of the step {worst:.3e}")
     assert worst < STEP_TOL[prec]
-
-
-def test_step_paper_scale_one_replica():
-    # SU(225) (L = 15, k = 4), ntrunc = 31: one replica of the benchmark step
-    L, k, nt, eps = 15, 4, 31, 0.01
-    n = L * L
-    u = series_links(L, k, nt, 0.5, 15)
-    eta = synth.langevin_noise(synth.rng_for(936), 1, n)
-    got = gpu_step(u, eta, L, k, nt, eps)
-    ref = nspt.langevin_step_replicas(u, eta, tek.twist_tensor(L, k), eps)
-    worst = max(order_errors(got[0, mu], ref[0, mu]).max() for mu in range(4))
-    print(f"N=225 ntrunc=31 step: worst per-order error {worst:.3e}")
-    assert worst < STEP_TOL["fp64"]
