@@ -170,6 +170,28 @@ pm_status polymat_mul_batched(const pm_problem* problems, int count,
                               size_t workspace_bytes, void* stream);
 
 /*
+ * polymat_mul_noalloc - polymat_mul without a workspace argument, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation).  The workspace is
+ * a file-scope device array of PM_NOALLOC_SCRATCH_BYTES bytes inside the
+ * library, one per GPU, held from the first use on that GPU until the
+ * process ends; the call itself allocates nothing.
+ *   A, B, C, n, ntrunc, precision, scale: as in polymat_mul.
+ *   stream: its device selects which GPU's array is used.
+ * Returns PM_ERR_UNSUPPORTED when polymat_workspace_size(n, ntrunc,
+ * precision, 1) exceeds PM_NOALLOC_SCRATCH_BYTES (e.g. N = 225 fits up to
+ * ntrunc = 31 in FP64 and up to ntrunc = 63 in FP32 and split BF16), and the
+ * errors of polymat_mul otherwise; nothing is enqueued on error.  Results
+ * equal those of polymat_mul bitwise (same kernels, same workspace layout).
+ * All calls on one GPU share its array: calls that may overlap in time on
+ * one GPU (different streams, different host threads) race and must be
+ * ordered by the caller.
+ */
+#define PM_NOALLOC_SCRATCH_BYTES (160u << 20)
+pm_status polymat_mul_noalloc(const void* A, const void* B, void* C, int n, int ntrunc,
+                              int precision, double scale, void* stream);
+
+/*
  * polymat_check_enable - opt-in finiteness check of polymat_mul and
  * polymat_mul_batched (process-wide, off by default).  The check itself runs
  * on the device in every call: the rescaling step records whether a

@@ -15,6 +15,7 @@ PM_OK, PM_ERR_INVALID, PM_ERR_WORKSPACE, PM_ERR_DEVICE, PM_ERR_UNSUPPORTED, PM_E
 PM_PREC_FP64, PM_PREC_FP32, PM_PREC_BF16X3 = range(3)
 PM_OP_N, PM_OP_C = 0, 1
 PM_MAX_NTRUNC = 63
+NOALLOC_SCRATCH_BYTES = 160 << 20   # PM_NOALLOC_SCRATCH_BYTES
 PHASES = ("rescale", "forward", "product", "inverse", "other", "retrunc")
 
 
@@ -57,6 +58,7 @@ SIGNATURES = {
     "polymat_transform_workspace_size": (_SZ, []),
     "polymat_timing_enable": (_I, [_I]),
     "polymat_check_enable": (_I, [_I]),
+    "polymat_mul_noalloc": (_I, [_VP, _VP, _VP, _I, _I, _I, _D, _VP]),
     "polymat_timing_read": (_I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
     "nspt_workspace_size": (_SZ, [_I, ctypes.POINTER(NsptParams), _I]),
     "nspt_langevin_step": (_I, [_VP, _VP, _I, ctypes.POINTER(NsptParams), _I, _VP, _SZ, _VP]),

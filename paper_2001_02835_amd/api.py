@@ -75,6 +75,24 @@ def polymat_mul(A: torch.Tensor, B: torch.Tensor, C: Optional[torch.Tensor] = No
     return C
 
 
+def polymat_mul_noalloc(A: torch.Tensor, B: torch.Tensor, C: Optional[torch.Tensor] = None,
+                        precision="fp64", scale: float = 0.0) -> torch.Tensor:
+    """C = A * B on the library's built-in device scratch array (no workspace
+    argument; products up to PM_NOALLOC_SCRATCH_BYTES of workspace)."""
+    _series_check(A, "A")
+    _series_check(B, "B")
+    if A.shape != B.shape or A.dim() != 3 or A.shape[1] != A.shape[2]:
+        raise ValueError("A and B must both have shape [ntrunc+1, n, n]")
+    if C is None:
+        C = torch.empty_like(A)
+    _series_check(C, "C")
+    nt, n = A.shape[0] - 1, A.shape[1]
+    st = nat.lib().polymat_mul_noalloc(A.data_ptr(), B.data_ptr(), C.data_ptr(), n, nt, _prec(precision),
+                                       float(scale), _stream_ptr(A.device))
+    nat.check(st, "polymat_mul_noalloc")
+    return C
+
+
 def _problems(items) -> ctypes.Array:
     arr = (nat.PmProblem * len(items))()
     for i, it in enumerate(items):

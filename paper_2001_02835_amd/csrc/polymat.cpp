@@ -317,6 +317,40 @@ pm_status plan_batch(const pm_problem* problems, int count, int prec, char* ws, 
   return PM_OK;
 }
 
+// ------------------------------------------- allocation-free single product
+//
+// polymat_mul_noalloc carves its workspace out of this file-scope device
+// array instead of a caller's buffer.  Each GPU the library runs on holds
+// its own copy (allocated with the code object, kept until the process
+// ends); host code never uses the array's name as an address: the device
+// address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kNoAllocBytes = static_cast<size_t>(PM_NOALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the device of `st` (looked up once per device).
+pm_status scratch_address(hipStream_t st, void** out) {
+  int cur = -1, dev = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return PM_ERR_DEVICE;
+  dev = cur;
+  if (st != nullptr && hipStreamGetDevice(st, &dev) != hipSuccess) return PM_ERR_DEVICE;
+  if (dev < 0 || dev >= kMaxDevices) return PM_ERR_DEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    if (dev != cur && hipSetDevice(dev) != hipSuccess) return PM_ERR_DEVICE;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (dev != cur) (void)hipSetDevice(cur);
+    if (e != hipSuccess || p == nullptr) return PM_ERR_DEVICE;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PM_OK;
+}
+
 }  // namespace
 
 namespace pm {
@@ -503,6 +537,22 @@ pm_status polymat_mul(const void* A, const void* B, void* C, int n, int ntrunc, 
   p.op_b = PM_OP_N;
   p.scale = scale;
   return polymat_mul_batched(&p, 1, precision, workspace, workspace_bytes, stream);
+}
+
+pm_status polymat_mul_noalloc(const void* A, const void* B, void* C, int n, int ntrunc, int precision,
+                              double scale, void* stream) {
+  // sizes first: a product whose workspace exceeds the built-in array is
+  // rejected before any HIP call
+  if (n < 1 || n > PM_MAX_N || ntrunc < 0 || !valid_prec(precision)) return PM_ERR_INVALID;
+  if (ntrunc > PM_MAX_NTRUNC) return PM_ERR_UNSUPPORTED;
+  const size_t need = polymat_workspace_size(n, ntrunc, precision, 1);
+  if (need == 0) return PM_ERR_INVALID;
+  if (need > kNoAllocBytes) return PM_ERR_UNSUPPORTED;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  void* ws = nullptr;
+  const pm_status s = scratch_address(st, &ws);
+  if (s) return s;
+  return polymat_mul(A, B, C, n, ntrunc, precision, scale, ws, kNoAllocBytes, stream);
 }
 
 size_t polymat_transform_workspace_size(void) { return align_up(sizeof(ScaleRec)); }

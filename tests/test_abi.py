@@ -54,6 +54,21 @@ def test_check_mode_switches_and_nonfinite_status_has_text():
     assert lib.polymat_check_enable(0) == nat.PM_OK
 
 
+def test_noalloc_rejects_sizes_before_any_device_call():
+    lib = pm.lib()
+    f = lib.polymat_mul_noalloc
+    assert f(FAKE_A, FAKE_B, FAKE_C, 0, 7, 0, 0.0, None) == nat.PM_ERR_INVALID         # n < 1
+    assert f(FAKE_A, FAKE_B, FAKE_C, 9, -1, 0, 0.0, None) == nat.PM_ERR_INVALID        # ntrunc < 0
+    assert f(FAKE_A, FAKE_B, FAKE_C, 9, 7, 3, 0.0, None) == nat.PM_ERR_INVALID         # bad precision
+    assert f(FAKE_A, FAKE_B, FAKE_C, 9, 64, 0, 0.0, None) == nat.PM_ERR_UNSUPPORTED    # ntrunc too large
+    # workspace beyond the built-in array: N = 300, ntrunc = 63, FP64
+    assert lib.polymat_workspace_size(300, 63, 0, 1) > nat.NOALLOC_SCRATCH_BYTES
+    assert f(FAKE_A, FAKE_B, FAKE_C, 300, 63, 0, 0.0, None) == nat.PM_ERR_UNSUPPORTED
+    # the largest benchmarked single products fit
+    for prec, nt in ((0, 31), (1, 63), (2, 63)):
+        assert 0 < lib.polymat_workspace_size(225, nt, prec, 1) <= nat.NOALLOC_SCRATCH_BYTES
+
+
 def test_transform_length():
     lib = pm.lib()
     assert [lib.polymat_transform_length(t) for t in (0, 1, 3, 7, 15, 31, 63, 5, 12)] == \
