@@ -40,14 +40,20 @@ def measure(sizes, steps=20):
             a = torch.from_numpy(synth.random_series(synth.rng_for(2, i, 0), n, nt, 0.5)).to(dev)
             b = torch.from_numpy(synth.random_series(synth.rng_for(2, i, 1), n, nt, 0.5)).to(dev)
             items.append(dict(A=a, B=b, C=torch.empty_like(a)))
-        # correctness of the configuration: one mode-wise product against a
-        # direct evaluation (the series product at ntrunc = 0 is A0 B0)
-        a0 = synth.random_series(synth.rng_for(3, n, 0), n, 0)
-        b0 = synth.random_series(synth.rng_for(3, n, 1), n, 0)
+        # correctness of the configuration: a short series product through the
+        # batched call (always the transform path, so the forced tile shape
+        # computes every mode product) against the convolution of eq. (5)
+        # evaluated directly with numpy
+        ntc = 3
+        a0 = synth.random_series(synth.rng_for(3, n, 0), n, ntc)
+        b0 = synth.random_series(synth.rng_for(3, n, 1), n, ntc)
+        ref = np.stack([sum(a0[l] @ b0[k - l] for l in range(k + 1)) for k in range(ntc + 1)])
         for prec in ("fp64", "fp32"):
-            c0 = pm.polymat_mul(torch.from_numpy(a0).to(dev), torch.from_numpy(b0).to(dev), precision=prec)
-            ref = a0[0] @ b0[0]
-            err = float(np.abs(c0.cpu().numpy()[0] - ref).max() / np.abs(ref).max())
+            chk = [dict(A=torch.from_numpy(a0).to(dev), B=torch.from_numpy(b0).to(dev),
+                        C=torch.empty((ntc + 1, n, n), dtype=torch.complex128, device=dev))]
+            pm.polymat_mul_batched(chk, precision=prec)
+            got = chk[0]["C"].cpu().numpy()
+            err = float(max(np.linalg.norm(got[k] - ref[k]) / np.linalg.norm(ref[k]) for k in range(ntc + 1)))
             if err > (1e-12 if prec == "fp64" else 1e-5):
                 raise SystemExit(f"config gives wrong products ({prec}, n={n}, err={err})")
             ws = pm.workspace(pm.batched_workspace_size(items, prec), dev)

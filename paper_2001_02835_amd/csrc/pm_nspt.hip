@@ -123,7 +123,11 @@ Layout layout(int R, const nspt_params* p, int prec) {
   l.fin = align_up(prec == PM_PREC_FP64 ? E * l.L * 16
                    : prec == PM_PREC_FP32 ? E * l.L * 8
                                           : static_cast<size_t>(bf16_ld(l.n)) * l.n * 8 * l.L);
-  l.fout = align_up(E * l.L * (prec == PM_PREC_FP64 ? 16 : 8));
+  // a G slot holds a product result (output format, length L) or, in the
+  // series exponential, a copy of Y^b in the input format at a length <= L/2;
+  // the split-BF16 rows are padded to 8 entries, which for n = 1 makes that
+  // copy larger than a result
+  l.fout = std::max(align_up(E * l.L * (prec == PM_PREC_FP64 ? 16 : 8)), l.fin);
   l.tser = align_up(E * l.nord * 16);
   size_t off = 0;
   l.rec = off;  off += align_up(sizeof(ScaleRec));

@@ -100,3 +100,17 @@ def test_step_precisions(prec):
     worst = max(order_errors(got[0, mu], ref[0, mu]).max() for mu in range(4))
     print(f"{prec}: worst per-order error of the step {worst:.3e}")
     assert worst < STEP_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("nt", [7, 31])
+def test_step_one_by_one_matrices_reduced_precisions(prec, nt):
+    # N = 1 (L = 1): the split-BF16 rows are padded to 8 entries, so the copies
+    # of Y^b at the shorter Horner lengths are larger than a product result
+    L, k, eps = 1, 0, 0.05
+    u = series_links(L, k, nt, 0.6, 17)
+    eta = synth.langevin_noise(synth.rng_for(937, nt), 1, 1)
+    got = gpu_step(u, eta, L, k, nt, eps, prec)
+    ref = nspt.langevin_step_replicas(u, eta, tek.twist_tensor(L, k), eps)
+    worst = max(order_errors(got[0, mu], ref[0, mu]).max() for mu in range(4))
+    assert worst < STEP_TOL[prec], worst
