@@ -250,7 +250,8 @@ enum {
   PM_PHASE_INVERSE = 3,   /* Steps 4-5: inverse transform, truncation, unscale */
   PM_PHASE_OTHER = 4,     /* NSPT element-wise passes (trace, force and noise) */
   PM_PHASE_RETRUNC = 5,   /* NSPT re-truncation of Fourier-space products */
-  PM_NUM_PHASES = 6
+  PM_PHASE_PIPELINE = 6,  /* persistent launch of all steps of an FP64 batch (and its set-up) */
+  PM_NUM_PHASES = 7
 };
 pm_status polymat_timing_enable(int on);
 pm_status polymat_timing_read(double* ms, int* launches);

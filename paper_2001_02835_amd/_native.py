@@ -16,7 +16,7 @@ PM_PREC_FP64, PM_PREC_FP32, PM_PREC_BF16X3 = range(3)
 PM_OP_N, PM_OP_C = 0, 1
 PM_MAX_NTRUNC = 63
 NOALLOC_SCRATCH_BYTES = 160 << 20   # PM_NOALLOC_SCRATCH_BYTES
-PHASES = ("rescale", "forward", "product", "inverse", "other", "retrunc")
+PHASES = ("rescale", "forward", "product", "inverse", "other", "retrunc", "pipeline")
 
 
 class PmProblem(ctypes.Structure):

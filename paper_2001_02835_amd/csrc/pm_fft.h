@@ -94,12 +94,14 @@ __device__ __forceinline__ double2 load_mode(const void* src, int E, int p, int 
 // (already rescaled), stored as modes 4q + R.  Every row k < L/2 of the tile
 // is read: the caller zero-fills the rows from nord on (branch-free loads let
 // the compiler interleave them with the arithmetic).
-template <int L, int R, FourierType FT>
-__device__ __forceinline__ void forward_residue(const double2 (*tile)[fft_ent<L>()], int lane,
+// S: lanes per matrix entry (1 or 2; the default is the stand-alone kernels' choice).
+template <int L, int R, FourierType FT, int S = fft_split<L>()>
+__device__ __forceinline__ void forward_residue(const double2 (*tile)[kEnt / S], int lane,
                                                 void* dst, int E, int n, int e, bool valid) {
   constexpr int M = L / 4;
-  constexpr int ENT = fft_ent<L>();
-  if constexpr (fft_split<L>() == 1) {
+  constexpr int ENT = kEnt / S;
+  static_assert(S == 1 || S == 2, "one or two lanes per entry");
+  if constexpr (S == 1) {
     double2 c[M];
     static_for<0, M>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
@@ -145,35 +147,36 @@ __device__ __forceinline__ void forward_residue(const double2 (*tile)[fft_ent<L>
   }
 }
 
-template <int L, FourierType FT>
-__device__ __forceinline__ void forward_from_tile(const double2 (*tile)[fft_ent<L>()], int lane, int r,
+template <int L, FourierType FT, int S = fft_split<L>()>
+__device__ __forceinline__ void forward_from_tile(const double2 (*tile)[kEnt / S], int lane, int r,
                                                   void* dst, int E, int n, int e, bool valid) {
   switch (r) {
-    case 0: forward_residue<L, 0, FT>(tile, lane, dst, E, n, e, valid); break;
-    case 1: forward_residue<L, 1, FT>(tile, lane, dst, E, n, e, valid); break;
-    case 2: forward_residue<L, 2, FT>(tile, lane, dst, E, n, e, valid); break;
-    default: forward_residue<L, 3, FT>(tile, lane, dst, E, n, e, valid); break;
+    case 0: forward_residue<L, 0, FT, S>(tile, lane, dst, E, n, e, valid); break;
+    case 1: forward_residue<L, 1, FT, S>(tile, lane, dst, E, n, e, valid); break;
+    case 2: forward_residue<L, 2, FT, S>(tile, lane, dst, E, n, e, valid); break;
+    default: forward_residue<L, 3, FT, S>(tile, lane, dst, E, n, e, valid); break;
   }
 }
 
 // ------------------------------------------------------------ inverse
 
 // Number of modes a lane loads for residue R, and the mode of its q-th one.
-template <int L> constexpr int lane_nmodes() { return L / 4 / fft_split<L>(); }
-template <int L, int R>
+template <int L, int S = fft_split<L>()> constexpr int lane_nmodes() { return L / 4 / S; }
+template <int L, int R, int S = fft_split<L>()>
 __device__ __forceinline__ int lane_mode(int q, int lane) {
-  if constexpr (fft_split<L>() == 1) return 4 * q + R;
-  else return 4 * (2 * q + (lane >= fft_ent<L>() ? 1 : 0)) + R;
+  if constexpr (S == 1) return 4 * q + R;
+  else return 4 * (2 * q + (lane >= kEnt / S ? 1 : 0)) + R;
 }
 
 // acc[k][el] <- sum_p Ct[p] w^{-kp} for all k < L/2 (no 1/L), from the modes
 // d[q] = Ct[lane_mode<L,R>(q)] of this lane (d is overwritten).  Ends with a
 // barrier, after which every wavefront may read acc.
-template <int L, int R>
-__device__ __forceinline__ void inverse_from_modes(double2* d, double2 (*acc)[fft_ent<L>()], int lane) {
+template <int L, int R, int S = fft_split<L>()>
+__device__ __forceinline__ void inverse_from_modes(double2* d, double2 (*acc)[kEnt / S], int lane) {
   constexpr int M = L / 4;
-  constexpr int ENT = fft_ent<L>();
-  if constexpr (fft_split<L>() == 1) {
+  constexpr int ENT = kEnt / S;
+  static_assert(S == 1 || S == 2, "one or two lanes per entry");
+  if constexpr (S == 1) {
     dft_inplace<M, -1>(d);
     auto term = [&](auto ki) {
       constexpr int k = decltype(ki)::value;
@@ -228,24 +231,24 @@ __device__ __forceinline__ void inverse_from_modes(double2* d, double2 (*acc)[ff
 }
 
 // Same, where load(p) returns mode p of this thread's entry.
-template <int L, int R, typename Load>
-__device__ __forceinline__ void inverse_residue(Load&& load, double2 (*acc)[fft_ent<L>()], int lane) {
-  constexpr int NQ = lane_nmodes<L>();
+template <int L, int R, int S, typename Load>
+__device__ __forceinline__ void inverse_residue(Load&& load, double2 (*acc)[kEnt / S], int lane) {
+  constexpr int NQ = lane_nmodes<L, S>();
   double2 d[NQ];
   static_for<0, NQ>([&](auto qi) {
     constexpr int q = decltype(qi)::value;
-    d[q] = load(lane_mode<L, R>(q, lane));
+    d[q] = load(lane_mode<L, R, S>(q, lane));
   });
-  inverse_from_modes<L, R>(d, acc, lane);
+  inverse_from_modes<L, R, S>(d, acc, lane);
 }
 
-template <int L, typename Load>
-__device__ __forceinline__ void inverse_to_lds(Load&& load, double2 (*acc)[fft_ent<L>()], int lane, int r) {
+template <int L, int S = fft_split<L>(), typename Load>
+__device__ __forceinline__ void inverse_to_lds(Load&& load, double2 (*acc)[kEnt / S], int lane, int r) {
   switch (r) {
-    case 0: inverse_residue<L, 0>(load, acc, lane); break;
-    case 1: inverse_residue<L, 1>(load, acc, lane); break;
-    case 2: inverse_residue<L, 2>(load, acc, lane); break;
-    default: inverse_residue<L, 3>(load, acc, lane); break;
+    case 0: inverse_residue<L, 0, S>(load, acc, lane); break;
+    case 1: inverse_residue<L, 1, S>(load, acc, lane); break;
+    case 2: inverse_residue<L, 2, S>(load, acc, lane); break;
+    default: inverse_residue<L, 3, S>(load, acc, lane); break;
   }
 }
 

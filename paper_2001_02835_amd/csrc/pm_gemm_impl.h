@@ -303,7 +303,8 @@ constexpr int cgemm2_min_waves() { return (WM * WN <= 2 && WGM * WGN == 8) ? 4 :
 // the contraction runs over (l, kk) for l = 0..k: C^(k) = sum_l opA(A)^(l)
 // opB(B)^(k-l), one K block of n per term (each block zero-padded to whole
 // chunks).
-template <typename T, int WM, int WN, int WGM, int WGN, bool OPA, bool OPB, bool G3, bool CONV = false>
+template <typename T, int WM, int WN, int WGM, int WGN, bool OPA, bool OPB, bool G3, bool CONV = false,
+          bool ONE_STAGE = false>
 __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, int tn, char* smem) {
   using C = Cx<T>;
   using T2 = typename C::T2;
@@ -349,7 +350,7 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
   // shapes, which fit in 128 registers) the loads of chunk c + 2 are in
   // flight while chunk c is multiplied and chunk c + 1 goes to LDS; with one
   // the loads run one chunk ahead.
-  constexpr bool PF2 = cgemm2_min_waves<WM, WN, WGM, WGN>() == 4;
+  constexpr bool PF2 = cgemm2_min_waves<WM, WN, WGM, WGN>() == 4 && !ONE_STAGE;
   constexpr int D = PF2 ? 2 : 1;
   struct Stage {
     T2 ra[G::LA], rb[G::LB];

@@ -22,6 +22,7 @@
 #include "pm_common.h"
 #include "pm_kernels.h"
 #include "pm_nspt.h"
+#include "pm_pipeline.h"
 
 namespace {
 
@@ -62,7 +63,7 @@ size_t result_bytes(int n, int L, int prec) {
 }
 
 struct ProductLayout {
-  size_t rec, partA, partB, At, Bt, Ct, total;
+  size_t rec, pipe, partA, partB, At, Bt, Ct, total;
 };
 
 ProductLayout product_layout(int n, int ntrunc, int prec) {
@@ -71,6 +72,7 @@ ProductLayout product_layout(int n, int ntrunc, int prec) {
   const size_t part = static_cast<size_t>(ntrunc + 1) * kNormChunks * sizeof(double);
   size_t off = 0;
   l.rec = off;   off += align_up(sizeof(ScaleRec));
+  l.pipe = off;  off += align_up(sizeof(PipeSlot));
   l.partA = off; off += align_up(part);
   l.partB = off; off += align_up(part);
   l.At = off;    off += align_up(operand_bytes(n, L, prec));
@@ -106,6 +108,25 @@ pm_status from_hip(hipError_t e) { return e == hipSuccess ? PM_OK : PM_ERR_DEVIC
 
 // Finiteness check of the product entry points (polymat_check_enable).
 std::atomic<bool> g_check{false};
+
+int env_int(const char* name, int dflt) {
+  const char* e = getenv(name);
+  if (!e || !*e) return dflt;
+  return atoi(e);
+}
+
+// POLYMAT_PIPELINE=1 routes FP64 batches through the persistent one-launch
+// pipeline (pm_pipeline.hip) instead of the staged launches; it is off by
+// default because on MI355X it is slower (the fused kernel's 128-register
+// budget and its per-ticket release fences cost more than the overlap of
+// transforms and products gains).  POLYMAT_PIPE_SPIN_LIMIT bounds each of its
+// waits (polls before the launch gives up and sets its abort flag).  Both are
+// read at every call.
+bool pipeline_enabled() { return env_int("POLYMAT_PIPELINE", 0) == 1; }
+unsigned int pipeline_spin_limit() {
+  const int v = env_int("POLYMAT_PIPE_SPIN_LIMIT", 1 << 20);
+  return v < 0 ? 0u : static_cast<unsigned int>(v);
+}
 
 bool stream_capturing(hipStream_t st) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -279,6 +300,119 @@ pm_status enqueue_products(const std::vector<Planned>& items, int prec, hipStrea
     }
     pm_status s = flush();
     if (s) return s;
+  }
+  return PM_OK;
+}
+
+// Compute units of the device that runs `st` (cached per device).
+int device_cus(hipStream_t st) {
+  static std::mutex mu;
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (st != nullptr && hipStreamGetDevice(st, &dev) != hipSuccess) return 0;
+  if (dev < 0 || dev >= 64) return 0;
+  std::lock_guard<std::mutex> lk(mu);
+  if (cus[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) return 0;
+    cus[dev] = v;
+  }
+  return cus[dev];
+}
+
+// True when no problem's C overlaps an operand of another problem: the
+// pipeline writes the first results while later problems are still being
+// read, so cross-problem aliasing keeps the batch on the staged launches.
+bool pipeline_alias_free(const std::vector<Planned>& items) {
+  if (items.size() > 256) return false;
+  for (size_t i = 0; i < items.size(); ++i) {
+    const Range c = range_of(items[i].pr.C, series_bytes(items[i].pr.n, items[i].pr.ntrunc));
+    for (size_t j = 0; j < items.size(); ++j) {
+      if (i == j) continue;
+      const size_t sb = series_bytes(items[j].pr.n, items[j].pr.ntrunc);
+      if (overlaps(c, range_of(items[j].pr.A, sb)) || overlaps(c, range_of(items[j].pr.B, sb))) return false;
+    }
+  }
+  return true;
+}
+
+// The whole FFT-CONV of a batch of FP64 products in one persistent launch per
+// kMaxPipeProblems problems (plus one small set-up launch per
+// kPipeInitChunk problems that writes the problem descriptors and clears the
+// counters).  The control block of each launch is returned in ctl (for the
+// status read-back of the finiteness check).
+pm_status enqueue_pipeline(const std::vector<Planned>& items, hipStream_t st, std::vector<const PipeSlot*>* ctl) {
+  const int cus = device_cus(st);
+  if (cus <= 0) return PM_ERR_DEVICE;
+  for (size_t c0 = 0; c0 < items.size(); c0 += kMaxPipeProblems) {
+    const int cn = static_cast<int>(std::min(items.size() - c0, static_cast<size_t>(kMaxPipeProblems)));
+    // largest product work first
+    std::vector<int> order(cn);
+    for (int k = 0; k < cn; ++k) order[k] = k;
+    auto work = [&](int k) {
+      const Planned& it = items[c0 + k];
+      return static_cast<double>(it.L) * it.pr.n * it.pr.n * it.pr.n;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+    PipeArgs pa{};
+    std::vector<PipeProblem> probs(cn);
+    for (int k = 0; k < cn; ++k) {
+      const Planned& it = items[c0 + order[k]];
+      PipeProblem& p = probs[k];
+      p.A = (const PM_GLOBAL double2*)(it.pr.A);
+      p.B = (const PM_GLOBAL double2*)(it.pr.B);
+      p.C = (PM_GLOBAL double2*)(it.pr.C);
+      p.At = (PM_GLOBAL double2*)(it.ws + it.lay.At);
+      p.Bt = (PM_GLOBAL double2*)(it.ws + it.lay.Bt);
+      p.Ct = (PM_GLOBAL double2*)(it.ws + it.lay.Ct);
+      p.partA = (PM_GLOBAL double*)(it.ws + it.lay.partA);
+      p.partB = (PM_GLOBAL double*)(it.ws + it.lay.partB);
+      p.rec = (PM_GLOBAL ScaleRec*)(it.ws + it.lay.rec);
+      p.scale = it.pr.scale;
+      p.n = it.pr.n;
+      p.nord = it.pr.ntrunc + 1;
+      p.ops = it.pr.op_a | (it.pr.op_b << 1);
+      pa.slot[k] = reinterpret_cast<PipeSlot*>(it.ws + it.lay.pipe);
+    }
+    for (int i0 = 0; i0 < cn; i0 += kPipeInitChunk) {
+      PipeInitArgs ia{};
+      ia.count = std::min(kPipeInitChunk, cn - i0);
+      for (int j = 0; j < ia.count; ++j) {
+        ia.probs[j] = probs[i0 + j];
+        ia.slot[j] = pa.slot[i0 + j];
+      }
+      ia.ctl = pa.slot[0];
+      ia.reset_ctl = i0 == 0;
+      pm_status s = from_hip(timed(PM_PHASE_PIPELINE, st, [&] { return launch_pipeline_init(ia, st); }));
+      if (s) return s;
+    }
+    // ticket order: iteration i holds SCALE(i-1), NORM(i), FWD(i-2), GEMM(i-3), INV(i-5)
+    unsigned int t = 0;
+    int ns = 0;
+    auto add = [&](int stage, int k) {
+      if (k < 0 || k >= cn) return;
+      const unsigned int c = pipe_count(probs[k], stage);
+      if (c == 0) return;
+      pa.segs[ns].start = t;
+      pa.segs[ns].stage = static_cast<unsigned short>(stage);
+      pa.segs[ns].prob = static_cast<unsigned short>(k);
+      ++ns;
+      t += c;
+    };
+    for (int i = 0; i < cn + 5; ++i) {
+      add(kStScale, i - 1);
+      add(kStNorm, i);
+      add(kStFwd, i - 2);
+      add(kStGemm, i - 3);
+      add(kStInv, i - 5);
+    }
+    pa.nseg = ns;
+    pa.total = t;
+    pa.spin_limit = pipeline_spin_limit();
+    pm_status s = from_hip(timed(PM_PHASE_PIPELINE, st, [&] { return launch_pipeline(pa, 2 * cus, st); }));
+    if (s) return s;
+    if (ctl) ctl->push_back(pa.slot[0]);
   }
   return PM_OK;
 }
@@ -469,10 +603,20 @@ pm_status polymat_mul_batched(const pm_problem* problems, int count, int precisi
   hipStream_t st = static_cast<hipStream_t>(stream);
   const bool check = g_check.load(std::memory_order_relaxed);
   if (check && stream_capturing(st)) return PM_ERR_INVALID;
-  s = enqueue_products(items, precision, st);
+  std::vector<const PipeSlot*> ctl;
+  if (precision == PM_PREC_FP64 && pipeline_enabled() && gemm_uses_g3() && pipeline_alias_free(items))
+    s = enqueue_pipeline(items, st, &ctl);
+  else
+    s = enqueue_products(items, precision, st);
   if (s || !check) return s;
-  // read back the status words of every product's scale record
+  // read back the status words of every product's scale record (and the
+  // abort flag of every pipeline launch: a wait that ran out)
   if (hipStreamSynchronize(st) != hipSuccess) return PM_ERR_DEVICE;
+  for (const PipeSlot* c : ctl) {
+    unsigned int ab = 0u;
+    if (hipMemcpy(&ab, &c->abort, sizeof(ab), hipMemcpyDeviceToHost) != hipSuccess || ab != 0u)
+      return PM_ERR_DEVICE;
+  }
   for (const Planned& it : items) {
     unsigned int flags[2] = {0u, 0u};
     const char* rec = it.ws + it.lay.rec + offsetof(ScaleRec, in_bad);

@@ -69,6 +69,74 @@ def test_uneven_64_product_batch(prec):
     print(f"uneven batch {prec}: max per-order error {worst:.3e} at (problem, (N, ntrunc), order) = {where}")
 
 
+def test_uneven_64_product_batch_one_launch_pipeline(monkeypatch):
+    """The same batch through the persistent one-launch pipeline
+    (POLYMAT_PIPELINE=1): every step of every product in one launch, tickets
+    ordered largest problem first and gated by per-problem counters."""
+    monkeypatch.setenv("POLYMAT_PIPELINE", "1")
+    shapes, ops = _cached("uneven_inputs", _uneven_inputs)
+    refs = _cached("uneven_oracle", _uneven_oracle)
+    items = []
+    for a, b in ops:
+        da = to_dev(a)
+        items.append(dict(A=da, B=to_dev(b), C=torch.empty_like(da), scale=0.0))
+    pm.timing_read()
+    pm.timing_enable(True)
+    pm.polymat_mul_batched(items, precision="fp64")
+    torch.cuda.synchronize()
+    pm.timing_enable(False)
+    ph = pm.timing_read()
+    assert ph["pipeline"][1] >= 2 and ph["product"][1] == 0     # set-up + one persistent launch
+    worst = 0.0
+    for i, (it, ref) in enumerate(zip(items, refs)):
+        e = order_errors(to_host(it["C"]), ref)
+        worst = max(worst, float(e.max()))
+        assert e.max() < TOL["fp64"], (i, shapes[i], e.max())
+    print(f"uneven batch, one-launch pipeline: max per-order error {worst:.3e}")
+
+
+@pytest.mark.parametrize("scale", [0.0, 1.0])
+def test_pipeline_mixed_operand_forms_and_ragged_sizes(monkeypatch, scale):
+    monkeypatch.setenv("POLYMAT_PIPELINE", "1")
+    shapes = [(1, 0), (9, 7), (65, 15), (33, 63), (130, 31), (17, 3), (64, 1), (100, 5)]
+    items, refs = [], []
+    for i, (n, nt) in enumerate(shapes):
+        a = synth.random_series(synth.rng_for(965, i, 0), n, nt, 0.8)
+        b = synth.random_series(synth.rng_for(965, i, 1), n, nt, 0.8)
+        op_a, op_b = i % 2, (i // 2) % 2
+        refs.append(ser.star(ser.dagger(a) if op_a else a, ser.dagger(b) if op_b else b))
+        items.append(dict(A=to_dev(a), B=to_dev(b), C=torch.empty((nt + 1, n, n), dtype=torch.complex128, device=DEV),
+                          op_a=op_a, op_b=op_b, scale=scale))
+    pm.polymat_mul_batched(items, precision="fp64")
+    for i, (it, ref) in enumerate(zip(items, refs)):
+        e = order_errors(to_host(it["C"]), ref)
+        assert e.max() < TOL["fp64"], (i, shapes[i], e.max())
+
+
+def test_pipeline_bounded_wait_aborts_and_reports(monkeypatch):
+    """With a spin limit of zero the first wait that is not already satisfied
+    gives up: the launch sets its abort flag and every work-group leaves, so
+    the kernel ends normally; with the finiteness check on the call reports
+    PM_ERR_DEVICE, and the next call with the normal limit is correct."""
+    monkeypatch.setenv("POLYMAT_PIPELINE", "1")
+    n, nt = 96, 31
+    a = synth.random_series(synth.rng_for(966, 0), n, nt, 0.5)
+    b = synth.random_series(synth.rng_for(966, 1), n, nt, 0.5)
+    da, db = to_dev(a), to_dev(b)
+    ws = pm.workspace(pm.workspace_size(n, nt, "fp64"), DEV)
+    monkeypatch.setenv("POLYMAT_PIPE_SPIN_LIMIT", "0")
+    pm.check_enable(True)
+    try:
+        with pytest.raises(pm.PolymatError) as ei:
+            pm.polymat_mul(da, db, precision="fp64", ws=ws)
+        assert ei.value.status == pm.PM_ERR_DEVICE
+    finally:
+        pm.check_enable(False)
+    monkeypatch.delenv("POLYMAT_PIPE_SPIN_LIMIT")
+    c = to_host(pm.polymat_mul(da, db, precision="fp64", ws=ws))
+    assert order_errors(c, ser.star(a, b)).max() < TOL["fp64"]
+
+
 # ------------------------------------------------- NSPT step at N = 225, ntrunc 31
 
 # tolerances of the updated links and of the increment U_new - U_old (orders
