@@ -493,14 +493,16 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
           }
       }
     }
-    if (wave_thin) {
-      // not speculated: other waves keep their MFMA stream free of this code
+    // marked unlikely so that the compiler keeps a branch here: turned into
+    // selects, this code would run in every wavefront and read the MFMA
+    // accumulators right after the MFMAs that write them
+    if (__builtin_expect(wave_thin, 0)) {
       asm volatile("");
 #pragma unroll
       for (int a = 0; a < WM; ++a)
 #pragma unroll
         for (int b = 0; b < WN; ++b)
-          if (thn[a][b]) {   // components 0 / 1 of the block's unused accumulator
+          if (__builtin_expect(thn[a][b], 0)) {   // components 0 / 1 of the block's unused accumulator
             c1[a][b][0] = fma(fa[a].x, fb[b].x, fma(-fa[a].y, fb[b].y, c1[a][b][0]));
             c1[a][b][1] = fma(fa[a].x, fb[b].y, fma(fa[a].y, fb[b].x, c1[a][b][1]));
           }
