@@ -118,8 +118,125 @@ __global__ __launch_bounds__(256) void k_norms(NormArgs args) {
   if (threadIdx.x == 0) jb.partial[k * kNormChunks + chunk] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// The stand-alone form of the choice of s (the computation of scale_wave in
+// pm_scale.h, with the per-order values broadcast through LDS, which is
+// faster than the cross-lane reads of the single-wavefront form).
 __global__ __launch_bounds__(64) void k_scale(ScaleArgs args) {
-  scale_wave(args.jobs[blockIdx.x], threadIdx.x);
+  const ScaleJob& jb = args.jobs[blockIdx.x];
+  const int nord = jb.nord;
+  const int tid = threadIdx.x;
+  double t = 0.0;
+  bool in_bad = false;
+  if (jb.fixed_s > 0.0) {
+    t = log(jb.fixed_s);
+  } else if (nord > 1) {
+    // per-order norms: lane k holds a_k, b_k (k < nord <= 64)
+    double na = 0.0, nb = 0.0;
+    if (tid < nord) {
+      double sa[4] = {0.0, 0.0, 0.0, 0.0}, sb[4] = {0.0, 0.0, 0.0, 0.0};
+      const int nsb = jb.nser_b > 0 ? jb.nser_b : jb.nser;
+      for (int q = 0; q < jb.nser; ++q) {
+        const double* pa = jb.partA + (q * nord + tid) * kNormChunks;
+#pragma unroll
+        for (int c = 0; c < kNormChunks; ++c) sa[c & 3] += pa[c];
+      }
+      for (int q = 0; q < nsb; ++q) {
+        const double* pb = jb.partB + (q * nord + tid) * kNormChunks;
+#pragma unroll
+        for (int c = 0; c < kNormChunks; ++c) sb[c & 3] += pb[c];
+      }
+      na = sqrt((sa[0] + sa[1]) + (sa[2] + sa[3]));
+      nb = sqrt((sb[0] + sb[1]) + (sb[2] + sb[3]));
+    }
+    in_bad = __any(!isfinite(na) || !isfinite(nb));
+    // orders below 1e-15 of an operand's largest one carry no information in
+    // FP64 (e.g. the rounding residue of a product at orders that vanish
+    // exactly); they are left out so that s is not chosen to lift them
+    double ma = na, mb = nb;
+    for (int off = 32; off > 0; off >>= 1) {
+      ma = fmax(ma, __shfl_xor(ma, off));
+      mb = fmax(mb, __shfl_xor(mb, off));
+    }
+    if (na < kNoiseFloor * ma) na = 0.0;
+    if (nb < kNoiseFloor * mb) nb = 0.0;
+    // c_m = sum_j a_j b_{m-j}: lane m holds c_m (m < 64) and c_{m+64}; the
+    // norms go through LDS so that the iterations do not wait on each other
+    __shared__ double a_s[64], b_s[64];
+    a_s[tid] = na;
+    b_s[tid] = nb;
+    __syncthreads();
+    double c0 = 0.0, c1 = 0.0;
+    const int nm = 2 * nord - 1;
+    for (int j = 0; j < nord; ++j) {
+      const double aj = a_s[j];
+      const int m0 = tid - j, m1 = tid + 64 - j;
+      const double b0 = b_s[m0 >= 0 && m0 < nord ? m0 : 0];
+      const double b1 = b_s[m1 >= 0 && m1 < nord ? m1 : 0];
+      if (m0 >= 0 && m0 < nord) c0 = fma(aj, b0, c0);
+      if (m1 >= 0 && m1 < nord && tid + 64 < nm) c1 = fma(aj, b1, c1);
+    }
+    const bool ok0 = tid < nm && c0 > 0.0 && isfinite(c0);
+    const bool ok1 = tid + 64 < nm && c1 > 0.0 && isfinite(c1);
+    const double lc0 = ok0 ? log(c0) : 0.0, lc1 = ok1 ? log(c1) : 0.0;
+    const double lmax0 = ok0 ? lc0 : -kAbsent, lmax1 = ok1 ? lc1 : -kAbsent;
+    const double lmin0 = (ok0 && tid < nord) ? lc0 : kAbsent;
+    const bool any = __any(ok0 && tid < nord);
+    if (any) {
+      // log c_m (or the absent marker) of every m, for broadcast reads
+      __shared__ double lmax_s[128], lmin_s[64];
+      lmax_s[tid] = lmax0;
+      lmax_s[tid + 64] = lmax1;
+      lmin_s[tid] = lmin0;
+      __syncthreads();
+      double lo = -300.0 / (2.0 * (nord - 1)), hi = -lo;
+      for (int round = 0; round < 3; ++round) {
+        const double step = (hi - lo) / 63.0;
+        const double tt = lo + step * tid;
+        // four independent max / min chains over m
+        double mx[4] = {-kAbsent, -kAbsent, -kAbsent, -kAbsent}, mn[4] = {kAbsent, kAbsent, kAbsent, kAbsent};
+#pragma unroll 2
+        for (int m = 0; m < 64; m += 4) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            mx[u] = fmax(mx[u], fma(static_cast<double>(m + u), tt, lmax_s[m + u]));
+            mn[u] = fmin(mn[u], fma(static_cast<double>(m + u), tt, lmin_s[m + u]));
+          }
+        }
+        // orders 64..nm-1 (present only when nord > 32; the absent ones read -kAbsent)
+        if (nm > 64) {
+#pragma unroll 2
+          for (int m = 64; m < 128; m += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) mx[u] = fmax(mx[u], fma(static_cast<double>(m + u), tt, lmax_s[m + u]));
+          }
+        }
+        // arg-min over lanes; near-ties (a flat objective, e.g. only one
+        // nonzero order) go to the candidate closest to t = 0 (s = 1)
+        double f = fmax(fmax(mx[0], mx[1]), fmax(mx[2], mx[3])) - fmin(fmin(mn[0], mn[1]), fmin(mn[2], mn[3]));
+        int idx = tid;
+        for (int off = 32; off > 0; off >>= 1) {
+          const double f2 = __shfl_xor(f, off);
+          const int i2 = __shfl_xor(idx, off);
+          const double tol = 1e-9 * fmax(1.0, fabs(f));
+          const double t1 = fabs(lo + step * idx), t2 = fabs(lo + step * i2);
+          const bool better = (f2 < f - tol) || (fabs(f2 - f) <= tol && (t2 < t1 || (t2 == t1 && i2 < idx)));
+          if (better) { f = f2; idx = i2; }
+        }
+        const double tb = lo + step * idx;
+        lo = tb - step;
+        hi = tb + step;
+        t = tb;
+      }
+    }
+  }
+  ScaleRec* rec = jb.rec;
+  if (tid == 0) {
+    rec->s = exp(t);
+    rec->in_bad = in_bad ? 1u : 0u;
+    rec->out_bad = 0u;
+  }
+  rec->spow[tid] = exp(t * tid);
+  rec->sinv[tid] = exp(-t * tid) / jb.L;
 }
 
 template <FourierType FT>
