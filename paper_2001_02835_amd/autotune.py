@@ -21,7 +21,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-NUM_CONFIGS = 10
+NUM_CONFIGS = 6
 
 
 def measure(sizes, steps=20):

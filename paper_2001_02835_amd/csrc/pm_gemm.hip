@@ -20,7 +20,7 @@ namespace {
 
 struct Shape { int wm, wn, wgm, wgn; };
 constexpr Shape kShapes[] = {
-#define PM_SHAPE(I, WM, WN, WGM, WGN, VER) {WM, WN, WGM, WGN},
+#define PM_SHAPE(I, WM, WN, WGM, WGN) {WM, WN, WGM, WGN},
     PM_GEMM_CONFIGS(PM_SHAPE)
 #undef PM_SHAPE
 };

@@ -6,9 +6,9 @@ namespace pm {
 
 hipError_t launch_gemm_f64(const GemmArgs& a, int cfg, bool g3, hipStream_t s) {
   switch (cfg) {
-#define PM_CASE(I, WM, WN, WGM, WGN, VER) \
+#define PM_CASE(I, WM, WN, WGM, WGN) \
   case I:                            \
-    return launch_cgemm_cfg<double, WM, WN, WGM, WGN, VER>(a, g3, s);
+    return launch_cgemm_cfg<double, WM, WN, WGM, WGN>(a, g3, s);
     PM_GEMM_CONFIGS(PM_CASE)
 #undef PM_CASE
     default:

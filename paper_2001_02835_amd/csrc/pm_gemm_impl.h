@@ -73,210 +73,8 @@ __device__ __forceinline__ bool uniform(bool b) { return __builtin_amdgcn_readfi
 // Re = P1 - P2, Im = P3 - P1 - P2.  It issues 3 MFMAs per k-step and block
 // instead of 4; the sums Xr + Xi and Yr + Yi are formed in registers from the
 // staged fragments, so memory traffic is unchanged.
-template <typename T, int WM, int WN, int WGM, int WGN, bool OPA, bool OPB, bool G3>
-__global__ __launch_bounds__(kWave * WGM * WGN) void k_cgemm(GemmArgs args) {
-  using C = Cx<T>;
-  using T2 = typename C::T2;
-  using Acc = typename C::Acc;
-  using G = GemmCfg<T, WM, WN, WGM, WGN>;
-  constexpr int BM = G::BM, BN = G::BN, BK = G::BK, NT = G::NT;
-  constexpr int PAD = C::kPad;
 
-  __shared__ T2 As[2][BK][BM + PAD];
-  __shared__ T2 Bs[2][BK][BN + PAD];
-
-  // ---- which job, mode and tile
-  const int id = xcd_remap(blockIdx.x, gridDim.x);
-  int jidx = 0;
-  for (int j = 1; j < args.njobs; ++j)
-    if (id >= args.jobs[j].tile_begin) jidx = j;
-  const GemmJob& jb = args.jobs[jidx];
-  const int local = id - jb.tile_begin;
-  const int per_mode = jb.tiles_m * jb.tiles_n;
-  const int p = local / per_mode;
-  const int rem = local - p * per_mode;
-  const int tm = rem / jb.tiles_n;
-  const int tn = rem - tm * jb.tiles_n;
-  const int n = jb.n, L = jb.L;
-  const size_t E = static_cast<size_t>(n) * n;
-  const int pa = OPA ? (L - p) % L : p;
-  const int pb = OPB ? (L - p) % L : p;
-  const T2* __restrict__ Ag = reinterpret_cast<const T2*>(jb.A) + pa * E;
-  const T2* __restrict__ Bg = reinterpret_cast<const T2*>(jb.B) + pb * E;
-  T2* __restrict__ Cg = reinterpret_cast<T2*>(jb.C) + static_cast<size_t>(p) * E;
-  const int row0 = tm * BM, col0 = tn * BN;
-
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
-  const int wave = tid / kWave;
-  const int wr = wave / WGN, wc = wave - (wave / WGN) * WGN;
-  const int wrow0 = wr * 16 * WM, wcol0 = wc * 16 * WN;
-  const int li = lane & 15, lk = lane >> 4;
-
-  // ---- per-thread staging coordinates (fixed over the K loop)
-  // A element (i, k): plain -> Ag[i][k] (coalesced along k); conjugated ->
-  // conj(Ag[k][i]) (coalesced along i).  Same idea for B with (k, j).
-  int a_i[G::LA], a_k[G::LA], b_j[G::LB], b_k[G::LB];
-#pragma unroll
-  for (int u = 0; u < G::LA; ++u) {
-    const int q = tid + NT * u;
-    if (!OPA) { a_k[u] = q % BK; a_i[u] = q / BK; } else { a_i[u] = q % BM; a_k[u] = q / BM; }
-  }
-#pragma unroll
-  for (int u = 0; u < G::LB; ++u) {
-    const int q = tid + NT * u;
-    if (!OPB) { b_j[u] = q % BN; b_k[u] = q / BN; } else { b_k[u] = q % BK; b_j[u] = q / BK; }
-  }
-
-  T2 ra[G::LA], rb[G::LB];
-  bool oka[G::LA], okb[G::LB];
-  // Branch-free loads: out-of-range elements read a clamped in-range address;
-  // they are replaced by zero only when written to LDS, so that the loads of
-  // the next chunk stay in flight while the current chunk is multiplied.
-  auto load_chunk = [&](int k0) {
-#pragma unroll
-    for (int u = 0; u < G::LA; ++u) {
-      const int gi = row0 + a_i[u], gk = k0 + a_k[u];
-      const bool ok = gi < n && gk < n;
-      const int ci = ok ? gi : 0, ck = ok ? gk : 0;
-      ra[u] = OPA ? Ag[static_cast<size_t>(ck) * n + ci] : Ag[static_cast<size_t>(ci) * n + ck];
-      oka[u] = ok;
-    }
-#pragma unroll
-    for (int u = 0; u < G::LB; ++u) {
-      const int gj = col0 + b_j[u], gk = k0 + b_k[u];
-      const bool ok = gj < n && gk < n;
-      const int cj = ok ? gj : 0, ck = ok ? gk : 0;
-      rb[u] = OPB ? Bg[static_cast<size_t>(cj) * n + ck] : Bg[static_cast<size_t>(ck) * n + cj];
-      okb[u] = ok;
-    }
-  };
-  auto store_chunk = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < G::LA; ++u) {
-      T2 v;
-      v.x = oka[u] ? ra[u].x : T(0);
-      v.y = oka[u] ? (OPA ? -ra[u].y : ra[u].y) : T(0);
-      As[buf][a_k[u]][a_i[u]] = v;
-    }
-#pragma unroll
-    for (int u = 0; u < G::LB; ++u) {
-      T2 v;
-      v.x = okb[u] ? rb[u].x : T(0);
-      v.y = okb[u] ? (OPB ? -rb[u].y : rb[u].y) : T(0);
-      Bs[buf][b_k[u]][b_j[u]] = v;
-    }
-  };
-
-  // 4-product form: cr, ci.  3-product form: cr = P1, ci = P2, c3 = P3.
-  Acc cr[WM][WN], ci[WM][WN], c3[G3 ? WM : 1][G3 ? WN : 1];
-#pragma unroll
-  for (int a = 0; a < WM; ++a)
-#pragma unroll
-    for (int b = 0; b < WN; ++b) { cr[a][b] = Acc{0, 0, 0, 0}; ci[a][b] = Acc{0, 0, 0, 0}; }
-  if constexpr (G3) {
-#pragma unroll
-    for (int a = 0; a < WM; ++a)
-#pragma unroll
-      for (int b = 0; b < WN; ++b) c3[a][b] = Acc{0, 0, 0, 0};
-  }
-
-  // wave-uniform activity of each 16x16 block (blocks fully outside the matrix are skipped)
-  bool act[WM][WN];
-#pragma unroll
-  for (int a = 0; a < WM; ++a)
-#pragma unroll
-    for (int b = 0; b < WN; ++b)
-      act[a][b] = uniform(row0 + wrow0 + 16 * a < n && col0 + wcol0 + 16 * b < n);
-
-  auto mma_step = [&](int buf, int s) {
-    const int kk = 4 * s + lk;
-    T2 fa[WM], fb[WN];
-#pragma unroll
-    for (int a = 0; a < WM; ++a) fa[a] = As[buf][kk][wrow0 + 16 * a + li];
-#pragma unroll
-    for (int b = 0; b < WN; ++b) fb[b] = Bs[buf][kk][wcol0 + 16 * b + li];
-    if constexpr (G3) {
-      T sa[WM], sb[WN];
-#pragma unroll
-      for (int a = 0; a < WM; ++a) sa[a] = fa[a].x + fa[a].y;
-#pragma unroll
-      for (int b = 0; b < WN; ++b) sb[b] = fb[b].x + fb[b].y;
-#pragma unroll
-      for (int a = 0; a < WM; ++a) {
-#pragma unroll
-        for (int b = 0; b < WN; ++b) {
-          if (act[a][b]) {
-            cr[a][b] = C::mfma(fa[a].x, fb[b].x, cr[a][b]);
-            ci[a][b] = C::mfma(fa[a].y, fb[b].y, ci[a][b]);
-            c3[a][b] = C::mfma(sa[a], sb[b], c3[a][b]);
-          }
-        }
-      }
-    } else {
-#pragma unroll
-      for (int a = 0; a < WM; ++a) {
-        const T nai = -fa[a].y;
-#pragma unroll
-        for (int b = 0; b < WN; ++b) {
-          if (act[a][b]) {
-            cr[a][b] = C::mfma(fa[a].x, fb[b].x, cr[a][b]);
-            ci[a][b] = C::mfma(fa[a].x, fb[b].y, ci[a][b]);
-          }
-        }
-#pragma unroll
-        for (int b = 0; b < WN; ++b) {
-          if (act[a][b]) {
-            cr[a][b] = C::mfma(nai, fb[b].y, cr[a][b]);
-            ci[a][b] = C::mfma(fa[a].y, fb[b].x, ci[a][b]);
-          }
-        }
-      }
-    }
-  };
-
-  const int nchunks = (n + BK - 1) / BK;
-  load_chunk(0);
-  store_chunk(0);
-  __syncthreads();
-  for (int c = 0; c < nchunks; ++c) {
-    const int buf = c & 1;
-    const int k0 = c * BK;
-    if (c + 1 < nchunks) load_chunk(k0 + BK);
-#pragma unroll
-    for (int s = 0; s < BK / 4; ++s)
-      if (k0 + 4 * s < n) mma_step(buf, s);
-    if (c + 1 < nchunks) store_chunk(buf ^ 1);
-    __syncthreads();
-  }
-
-  // ---- epilogue: interleave re/im and store the tile
-#pragma unroll
-  for (int a = 0; a < WM; ++a) {
-#pragma unroll
-    for (int b = 0; b < WN; ++b) {
-      const int gj = col0 + wcol0 + 16 * b + li;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int gi = row0 + wrow0 + 16 * a + C::out_row(lane, v);
-        if (gi < n && gj < n) {
-          T2 o;
-          if constexpr (G3) {
-            o.x = cr[a][b][v] - ci[a][b][v];
-            o.y = c3[a][b][v] - cr[a][b][v] - ci[a][b][v];
-          } else {
-            o.x = cr[a][b][v];
-            o.y = ci[a][b][v];
-          }
-          Cg[static_cast<size_t>(gi) * n + gj] = o;
-        }
-      }
-    }
-  }
-}
-
-
-// Second form of the kernel: both operand tiles are staged k-major in LDS
+// The kernel: both operand tiles are staged k-major in LDS
 // (A as [k][i], B as [k][j], rows padded by one element), so that every
 // fragment read is a contiguous run across the 16 lanes of a lane group, and
 // the k index is permuted across the lane groups of the MFMA: in k-step s of
@@ -624,17 +422,13 @@ __global__ __launch_bounds__(kWave * WGM * WGN, (cgemm2_min_waves<WM, WN, WGM, W
 }  // namespace gemm_detail
 
 // Launch the interleaved-complex product kernel with one tile configuration.
-template <typename T, int WM, int WN, int WGM, int WGN, int VER>
+template <typename T, int WM, int WN, int WGM, int WGN>
 hipError_t launch_cgemm_cfg(const GemmArgs& a, bool g3, hipStream_t s) {
   using namespace gemm_detail;
   const int oa = a.jobs[0].opA, ob = a.jobs[0].opB;   // shared by all jobs of a launch
   constexpr int nt = kWave * WGM * WGN;
   const int g = a.total_tiles;
-#define PM_K(OA, OB, G3)                                                           \
-  do {                                                                             \
-    if constexpr (VER == 2) k_cgemm2<T, WM, WN, WGM, WGN, OA, OB, G3><<<g, nt, 0, s>>>(a); \
-    else k_cgemm<T, WM, WN, WGM, WGN, OA, OB, G3><<<g, nt, 0, s>>>(a);              \
-  } while (0)
+#define PM_K(OA, OB, G3) k_cgemm2<T, WM, WN, WGM, WGN, OA, OB, G3><<<g, nt, 0, s>>>(a)
   if (g3) {
     if (!oa && !ob) PM_K(false, false, true);
     else if (!oa && ob) PM_K(false, true, true);
@@ -676,15 +470,11 @@ hipError_t launch_cgemm_conv(const GemmArgs& a, bool g3, hipStream_t s) {
 // Tile configurations (blocks of 16 x 16 per wavefront WM x WN, wavefronts per
 // work-group WGM x WGN).  Index order is part of the tuning table.
 #define PM_GEMM_CONFIGS(X)  \
-  X(0, 2, 2, 2, 2, 1)         \
-  X(1, 2, 2, 4, 2, 1)         \
-  X(2, 2, 1, 2, 4, 1)         \
-  X(3, 1, 4, 4, 1, 1)         \
-  X(4, 2, 2, 2, 2, 2)         \
-  X(5, 2, 2, 4, 2, 2)         \
-  X(6, 2, 1, 2, 4, 2)         \
-  X(7, 1, 4, 4, 1, 2)         \
-  X(8, 2, 4, 2, 1, 2)         \
-  X(9, 4, 2, 1, 2, 2)
+  X(0, 2, 2, 2, 2)          \
+  X(1, 2, 2, 4, 2)          \
+  X(2, 2, 1, 2, 4)          \
+  X(3, 1, 4, 4, 1)          \
+  X(4, 2, 4, 2, 1)          \
+  X(5, 4, 2, 1, 2)
 
 }  // namespace pm

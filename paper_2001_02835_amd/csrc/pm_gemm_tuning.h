@@ -7,7 +7,7 @@
 namespace pm {
 
 struct TuneRow { int n_max, cfg; };
-constexpr TuneRow kTune_fp64[] = {{92, 6}, {145, 2}, {197, 2}, {257, 6}, {1073741824, 6}};
-constexpr TuneRow kTune_fp32[] = {{92, 6}, {145, 1}, {197, 6}, {257, 5}, {1073741824, 6}};
+constexpr TuneRow kTune_fp64[] = {{92, 2}, {145, 2}, {197, 2}, {257, 2}, {1073741824, 2}};
+constexpr TuneRow kTune_fp32[] = {{92, 2}, {145, 2}, {197, 2}, {257, 2}, {1073741824, 2}};
 
 }  // namespace pm

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -242,9 +243,18 @@ pm_status enqueue_products(const std::vector<Planned>& items, int prec, hipStrea
     pm_status s = flush();
     if (s) return s;
   }
-  // 4. mode-wise products, one launch per (operand form, tile configuration)
+  // 4. mode-wise products, one launch per (operand form, tile configuration,
+  // matrix size): the tiles of one launch then cost the same, so the equal
+  // shares of tiles that the XCD-contiguous tile order gives the eight XCDs
+  // are equal shares of work (a launch mixing sizes leaves the XCDs that hold
+  // the large problems' tiles running after the others)
   {
+    std::vector<int> sizes;
+    for (const Planned& it : items) sizes.push_back(it.pr.n);
+    std::sort(sizes.begin(), sizes.end(), std::greater<int>());
+    sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
     const int ncfg = gemm_num_configs(ft);
+    for (int nsz : sizes) {
     for (int form = 0; form < 4; ++form) {
       for (int cfg = 0; cfg < ncfg; ++cfg) {
         GemmArgs ga{};
@@ -257,7 +267,7 @@ pm_status enqueue_products(const std::vector<Planned>& items, int prec, hipStrea
           return s;
         };
         for (const Planned& it : items) {
-          if (it.pr.op_a * 2 + it.pr.op_b != form || gemm_config(ft, it.pr.n) != cfg) continue;
+          if (it.pr.n != nsz || it.pr.op_a * 2 + it.pr.op_b != form || gemm_config(ft, it.pr.n) != cfg) continue;
           if (ga.njobs == kMaxGemmJobs) { pm_status s = flush(); if (s) return s; }
           GemmJob& j = ga.jobs[ga.njobs++];
           j.A = it.ws + it.lay.At;
@@ -275,6 +285,7 @@ pm_status enqueue_products(const std::vector<Planned>& items, int prec, hipStrea
         pm_status s = flush();
         if (s) return s;
       }
+    }
     }
   }
   // 5. inverse transforms, truncation and unscaling into C
