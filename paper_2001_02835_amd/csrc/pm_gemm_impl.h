@@ -32,7 +32,12 @@ template <typename T> struct Cx;
 template <> struct Cx<double> {
   using T2 = double2;
   using Acc = d4;
-  static constexpr int kPad = 1;   // LDS row pad (elements): 65 * 16 B = 4 banks shift
+  // LDS tile of BK = 16 rows of W elements (see the layout note at Tile2):
+  // rows of W elements, every fourth row start moved on by 4 elements, and
+  // the two low bits of the column XOR-ed with k & 3
+  static constexpr bool kSwizzle = true;
+  __host__ __device__ static constexpr int tile_elems(int W) { return 16 * W + 16; }
+  __device__ static __forceinline__ int lds(int W, int k, int x) { return k * W + (k >> 2) * 4 + (x ^ (k & 3)); }
   __device__ static __forceinline__ Acc mfma(double a, double b, Acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -42,7 +47,10 @@ template <> struct Cx<double> {
 template <> struct Cx<float> {
   using T2 = float2;
   using Acc = f4;
-  static constexpr int kPad = 2;
+  // LDS tile: rows of W + 1 elements
+  static constexpr bool kSwizzle = false;
+  __host__ __device__ static constexpr int tile_elems(int W) { return 16 * (W + 1); }
+  __device__ static __forceinline__ int lds(int W, int k, int x) { return k * (W + 1) + x; }
   __device__ static __forceinline__ Acc mfma(float a, float b, Acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -74,20 +82,34 @@ __device__ __forceinline__ bool uniform(bool b) { return __builtin_amdgcn_readfi
 // instead of 4; the sums Xr + Xi and Yr + Yi are formed in registers from the
 // staged fragments, so memory traffic is unchanged.
 
-// The kernel: both operand tiles are staged k-major in LDS
-// (A as [k][i], B as [k][j], rows padded by one element), so that every
-// fragment read is a contiguous run across the 16 lanes of a lane group, and
-// the k index is permuted across the lane groups of the MFMA: in k-step s of
-// a chunk, lane group g (lanes 16g..16g+15) contracts over k = 4g + s.  The
-// MFMA only needs A and B to agree on that assignment.  The fragments of the
-// next k-step are read from LDS while the current MFMAs issue.
+// The kernel: both operand tiles are staged k-major in LDS (A as [k][i], B
+// as [k][j]), so that every fragment read is a run of 16 elements across the
+// 16 lanes of a lane group, and the k index is permuted across the lane
+// groups of the MFMA (the MFMA only needs A and B to agree on it).  The
+// fragments of the next k-step are read from LDS while the current MFMAs
+// issue.
+//
+// Layout of the 16-byte (FP64 complex) elements.  A 128-bit LDS read of a
+// wavefront runs at full rate on gfx950 (measured) when the four lane groups
+// see the same arrangement of 16-byte slots within 256 bytes, up to a common
+// shift and an XOR of the slot index by 0..3 that may differ per group; rows
+// of 65 elements read by different groups (a different rotation per group)
+// cost four times the cycles.  The FP64 tiles therefore use rows of W = 64
+// elements (1 KB, so that rows start on the same slot), every block of four
+// rows moved on by 4 elements (64 bytes), and the two low bits of the column
+// XOR-ed with k & 3; in k-step s lane group g contracts k = g + 4 s.  A
+// fragment read of k-step s then sees slot (li ^ g) + 4 s in lane li of group
+// g (a common shift and a per-group XOR), with the k-step in the address
+// offset only; the transposed stores of A (16 lanes writing one column of 16
+// rows) land in 16 distinct slots.  The FP32 tiles (8-byte elements, 64-bit
+// reads) keep rows of 65 elements and k = 4 g + s.
 template <typename T, int WM, int WN, int WGM, int WGN>
 struct Tile2 {
   using T2 = typename Cx<T>::T2;
   using G = GemmCfg<T, WM, WN, WGM, WGN>;
   static constexpr int BM = G::BM, BN = G::BN, BK = G::BK;
-  static constexpr int kAElems = 2 * BK * (BM + 1);
-  static constexpr int kBElems = 2 * BK * (BN + 1);
+  static constexpr int kAElems = 2 * Cx<T>::tile_elems(BM);
+  static constexpr int kBElems = 2 * Cx<T>::tile_elems(BN);
   static constexpr size_t kLdsBytes = sizeof(T2) * (kAElems + kBElems);
 };
 
@@ -109,10 +131,11 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
   using Acc = typename C::Acc;
   using G = GemmCfg<T, WM, WN, WGM, WGN>;
   constexpr int BM = G::BM, BN = G::BN, BK = G::BK, NT = G::NT;
-  typedef T2 ATile[BK][BM + 1];
-  typedef T2 BTile[BK][BN + 1];
-  ATile* As = reinterpret_cast<ATile*>(smem);
-  BTile* Bs = reinterpret_cast<BTile*>(smem + sizeof(T2) * Tile2<T, WM, WN, WGM, WGN>::kAElems);
+  constexpr int TA = C::tile_elems(BM), TB = C::tile_elems(BN);
+  // the k of lane group g in k-step s
+  auto kidx = [](int g, int s) { return C::kSwizzle ? g + 4 * s : 4 * g + s; };
+  T2* As = reinterpret_cast<T2*>(smem);                                   // [2][TA]
+  T2* Bs = reinterpret_cast<T2*>(smem + sizeof(T2) * Tile2<T, WM, WN, WGM, WGN>::kAElems);   // [2][TB]
 
   const int n = jb.n, L = jb.L;
   const size_t E = static_cast<size_t>(n) * n;
@@ -127,8 +150,14 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
-  const int wr = wave / WGN, wc = wave - (wave / WGN) * WGN;
-  const int wrow0 = wr * 16 * WM, wcol0 = wc * 16 * WN;
+  // wavefront (wr, wc) owns the 16 x 16 blocks (wr + WGM a, wc + WGN b) of the
+  // tile.  Interleaved this way, the blocks of a ragged edge tile that lie
+  // inside the matrix are spread over all wavefronts instead of leaving whole
+  // wavefronts idle; wr varies fastest with the wavefront index, so that the
+  // wavefronts of one SIMD (w, w + 4, ...) take different tile columns.
+  const int wr = wave % WGM, wc = wave / WGM;
+  auto brow = [&](int a) { return 16 * (wr + WGM * a); };
+  auto bcol = [&](int b) { return 16 * (wc + WGN * b); };
   const int li = lane & 15, lg = lane >> 4;
 
   // staging coordinates: tile element (i, kk) of A and (kk, j) of B
@@ -190,14 +219,14 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
       T2 v;
       v.x = S.oka[u] ? S.ra[u].x : T(0);
       v.y = S.oka[u] ? (OPA ? -S.ra[u].y : S.ra[u].y) : T(0);
-      As[buf][a_k[u]][a_i[u]] = v;
+      As[buf * TA + C::lds(BM, a_k[u], a_i[u])] = v;
     }
 #pragma unroll
     for (int u = 0; u < G::LB; ++u) {
       T2 v;
       v.x = S.okb[u] ? S.rb[u].x : T(0);
       v.y = S.okb[u] ? (OPB ? -S.rb[u].y : S.rb[u].y) : T(0);
-      Bs[buf][b_k[u]][b_j[u]] = v;
+      Bs[buf * TB + C::lds(BN, b_k[u], b_j[u])] = v;
     }
   };
 
@@ -214,7 +243,7 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
   // single row / column of C.  Instead of a whole 16x16 MFMA block, such a
   // block is accumulated on the vector unit (about 1/16 of the work): its
   // fragment of the thin side is the broadcast of the one row (column) of the
-  // operand, every lane sums its own k subset (k = 4 g + s) of the complex
+  // operand, every lane sums its own k subset (its k of every k-step) of the complex
   // product into components 0 (re) and 1 (im) of the block's unused MFMA
   // accumulator, and the four lane groups are summed at the end.  This removes
   // 2/(m+1) of the MFMA work.
@@ -223,13 +252,13 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
   bool rin[WM], cin[WN], trow[WM], tcol[WN];
 #pragma unroll
   for (int a = 0; a < WM; ++a) {
-    rin[a] = uniform(row0 + wrow0 + 16 * a < n);
-    trow[a] = uniform(thin && row0 + wrow0 + 16 * a == edge);
+    rin[a] = uniform(row0 + brow(a) < n);
+    trow[a] = uniform(thin && row0 + brow(a) == edge);
   }
 #pragma unroll
   for (int b = 0; b < WN; ++b) {
-    cin[b] = uniform(col0 + wcol0 + 16 * b < n);
-    tcol[b] = uniform(thin && col0 + wcol0 + 16 * b == edge);
+    cin[b] = uniform(col0 + bcol(b) < n);
+    tcol[b] = uniform(thin && col0 + bcol(b) == edge);
   }
   bool act[WM][WN], thn[WM][WN];
 #pragma unroll
@@ -248,18 +277,18 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
   // (column) in every lane
   int frow[WM], fcol[WN];
 #pragma unroll
-  for (int a = 0; a < WM; ++a) frow[a] = wrow0 + 16 * a + (trow[a] ? 0 : li);
+  for (int a = 0; a < WM; ++a) frow[a] = brow(a) + (trow[a] ? 0 : li);
 #pragma unroll
-  for (int b = 0; b < WN; ++b) fcol[b] = wcol0 + 16 * b + (tcol[b] ? 0 : li);
+  for (int b = 0; b < WN; ++b) fcol[b] = bcol(b) + (tcol[b] ? 0 : li);
 
   // fragments of one k-step; the next k-step's fragments are read from LDS
   // while the current MFMAs issue
   auto read_frags = [&](int buf, int s, T2 (&fa)[WM], T2 (&fb)[WN]) {
-    const int kk = 4 * lg + s;
+    const int kk = kidx(lg, s);
 #pragma unroll
-    for (int a = 0; a < WM; ++a) fa[a] = As[buf][kk][frow[a]];
+    for (int a = 0; a < WM; ++a) fa[a] = As[buf * TA + C::lds(BM, kk, frow[a])];
 #pragma unroll
-    for (int b = 0; b < WN; ++b) fb[b] = Bs[buf][kk][fcol[b]];
+    for (int b = 0; b < WN; ++b) fb[b] = Bs[buf * TB + C::lds(BN, kk, fcol[b])];
   };
   auto mma = [&](const T2 (&fa)[WM], const T2 (&fb)[WN]) {
     if constexpr (G3) {
@@ -311,39 +340,49 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
   // one chunk: cur holds chunk c + 1 (stored to the other LDS buffer after
   // the products), nxt receives the loads of chunk c + D (with one stage
   // both are the same registers)
+  //
+  // Every global load, LDS read and LDS store of a chunk is issued whatever
+  // the chunk's position, and only the MFMAs are conditional, so that the
+  // compiler counts the loads in flight exactly and waits only for the ones a
+  // store or a product needs (a load issued under a branch makes it wait for
+  // every load).  Past the end the last chunk is loaded again, a k-step
+  // beyond n reads LDS rows that are never multiplied, and the store after
+  // the last chunk fills the idle LDS buffer: all in bounds and without
+  // effect.
   auto chunk = [&](int c, const Stage& cur, Stage& nxt) {
     const int buf = c & 1;
     const int k0 = chunk_k0(c);
-    if (c + D < nchunks) load_chunk(c + D, nxt);
-    // k-step s of the chunk contracts k = k0 + 4 g + s; it is needed when k0 + s < n
+    load_chunk(c + D < nchunks ? c + D : nchunks - 1, nxt);
+    // k-step s of the chunk contracts k = k0 + kidx(g, s); it is needed when its
+    // smallest k, k0 + kidx(0, s), is below n
     T2 fa0[WM], fb0[WN], fa1[WM], fb1[WN];
     read_frags(buf, 0, fa0, fb0);
-    if (k0 + 1 < n) read_frags(buf, 1, fa1, fb1);
+    read_frags(buf, 1, fa1, fb1);
     mma(fa0, fb0);
-    if (k0 + 1 < n) {
-      if (k0 + 2 < n) read_frags(buf, 2, fa0, fb0);
-      mma(fa1, fb1);
-      if (k0 + 2 < n) {
-        if (k0 + 3 < n) read_frags(buf, 3, fa1, fb1);
-        mma(fa0, fb0);
-        if (k0 + 3 < n) mma(fa1, fb1);
-      }
-    }
-    if (c + 1 < nchunks) store_chunk(buf ^ 1, cur);
+    read_frags(buf, 2, fa0, fb0);
+    if (k0 + kidx(0, 1) < n) mma(fa1, fb1);
+    read_frags(buf, 3, fa1, fb1);
+    if (k0 + kidx(0, 2) < n) mma(fa0, fb0);
+    if (k0 + kidx(0, 3) < n) mma(fa1, fb1);
+    store_chunk(buf ^ 1, cur);
     __syncthreads();
   };
   load_chunk(0, st0);
   store_chunk(0, st0);
   if constexpr (PF2) {
-    if (nchunks > 1) load_chunk(1, st1);
+    load_chunk(nchunks > 1 ? 1 : 0, st1);
   }
   __syncthreads();
   if constexpr (PF2) {
-    // pairs of chunks, so that the two stages keep fixed registers
-    for (int c = 0; c < nchunks; c += 2) {
+    // pairs of chunks, so that the two stages keep fixed registers (an odd
+    // last chunk after the loop keeps the loop body free of branches around
+    // memory instructions)
+    int c = 0;
+    for (; c + 1 < nchunks; c += 2) {
       chunk(c, st1, st0);
-      if (c + 1 < nchunks) chunk(c + 1, st0, st1);
+      chunk(c + 1, st0, st1);
     }
+    if (c < nchunks) chunk(c, st1, st0);
   } else {
     for (int c = 0; c < nchunks; ++c) chunk(c, st0, st0);
   }
@@ -353,10 +392,10 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
 #pragma unroll
     for (int b = 0; b < WN; ++b) {
       if (!act[a][b]) continue;
-      const int gj = col0 + wcol0 + 16 * b + li;
+      const int gj = col0 + bcol(b) + li;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int gi = row0 + wrow0 + 16 * a + C::out_row(lane, v);
+        const int gi = row0 + brow(a) + C::out_row(lane, v);
         if (gi < n && gj < n) {
           T2 o;
           if constexpr (G3) {
@@ -386,8 +425,8 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
       T2 o;
       o.x = re;
       o.y = im;
-      const int gi = trow[a] ? edge : row0 + wrow0 + 16 * a + li;
-      const int gj = tcol[b] ? edge : col0 + wcol0 + 16 * b + li;
+      const int gi = trow[a] ? edge : row0 + brow(a) + li;
+      const int gj = tcol[b] ? edge : col0 + bcol(b) + li;
       const bool mine = (trow[a] && tcol[b]) ? lane == 0 : lg == 0;
       if (mine && gi < n && gj < n) Cg[static_cast<size_t>(gi) * n + gj] = o;
     }
