@@ -337,35 +337,41 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
   };
 
   const int nchunks = CONV ? (p + 1) * cpl : cpl;
-  // one chunk: cur holds chunk c + 1 (stored to the other LDS buffer after
-  // the products), nxt receives the loads of chunk c + D (with one stage
-  // both are the same registers)
+  // One chunk.  cur holds chunk c + 1 (stored to the other LDS buffer), nxt
+  // receives the loads of chunk c + D (with one stage both are the same
+  // registers); on entry fa0 / fb0 hold the fragments of k-step 0.  The
+  // store of chunk c + 1 and the barrier come after the third k-step's
+  // products: the other buffer was last read before the previous barrier,
+  // and every read of this chunk is issued by then.  The fragments of the
+  // next chunk's k-step 0 are read right after the barrier, while the last
+  // k-step's products run, so that the matrix cores have work across the
+  // barrier.
   //
   // Every global load, LDS read and LDS store of a chunk is issued whatever
   // the chunk's position, and only the MFMAs are conditional, so that the
   // compiler counts the loads in flight exactly and waits only for the ones a
   // store or a product needs (a load issued under a branch makes it wait for
   // every load).  Past the end the last chunk is loaded again, a k-step
-  // beyond n reads LDS rows that are never multiplied, and the store after
-  // the last chunk fills the idle LDS buffer: all in bounds and without
-  // effect.
+  // beyond n reads LDS rows that are never multiplied, and the store and the
+  // reads after the last chunk touch the idle LDS buffer: all in bounds and
+  // without effect.
+  T2 fa0[WM], fb0[WN], fa1[WM], fb1[WN];
   auto chunk = [&](int c, const Stage& cur, Stage& nxt) {
     const int buf = c & 1;
     const int k0 = chunk_k0(c);
     load_chunk(c + D < nchunks ? c + D : nchunks - 1, nxt);
     // k-step s of the chunk contracts k = k0 + kidx(g, s); it is needed when its
     // smallest k, k0 + kidx(0, s), is below n
-    T2 fa0[WM], fb0[WN], fa1[WM], fb1[WN];
-    read_frags(buf, 0, fa0, fb0);
     read_frags(buf, 1, fa1, fb1);
     mma(fa0, fb0);
     read_frags(buf, 2, fa0, fb0);
     if (k0 + kidx(0, 1) < n) mma(fa1, fb1);
     read_frags(buf, 3, fa1, fb1);
     if (k0 + kidx(0, 2) < n) mma(fa0, fb0);
-    if (k0 + kidx(0, 3) < n) mma(fa1, fb1);
     store_chunk(buf ^ 1, cur);
     __syncthreads();
+    read_frags(buf ^ 1, 0, fa0, fb0);
+    if (k0 + kidx(0, 3) < n) mma(fa1, fb1);
   };
   load_chunk(0, st0);
   store_chunk(0, st0);
@@ -373,6 +379,7 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
     load_chunk(nchunks > 1 ? 1 : 0, st1);
   }
   __syncthreads();
+  read_frags(0, 0, fa0, fb0);
   if constexpr (PF2) {
     // pairs of chunks, so that the two stages keep fixed registers (an odd
     // last chunk after the loop keeps the loop body free of branches around
