@@ -248,7 +248,9 @@ def bench_crossover(torch, synth, pm, dev, reps=20):
     """Naive-CONV (direct eq. (5)) against FFT-CONV for one FP64 product at
     N=225 and growing ntrunc (entries N(0,1)*0.5^k): where the transform pays."""
     n = 225
-    res = {"workload": "1 product N=225, FP64, entries N(0,1)*0.5^k; ms per product", "points": []}
+    res = {"workload": "1 product N=225, FP64, entries N(0,1)*0.5^k; ms per product (in_chain_fftconv_ms: "
+                       "forward + product + inverse phases, the cost of one product inside a Fourier-space chain)",
+           "points": []}
     for nt in (0, 1, 2, 3, 5, 7, 15, 31):
         a = torch.from_numpy(synth.random_series(synth.rng_for(7, nt, 0), n, nt, 0.5)).to(dev)
         b = torch.from_numpy(synth.random_series(synth.rng_for(7, nt, 1), n, nt, 0.5)).to(dev)
@@ -269,8 +271,22 @@ def bench_crossover(torch, synth, pm, dev, reps=20):
             e1.record()
             torch.cuda.synchronize()
             t[name] = e0.elapsed_time(e1) / reps
+        # phases of the FFT-CONV call: inside a chain of products that stays in
+        # Fourier space (the Horner steps of the series exponential) a product
+        # costs its product phase plus one re-truncation (an inverse and a
+        # forward transform in one pass), without the rescale
+        pm.timing_read()
+        pm.timing_enable(True)
+        for _ in range(reps):
+            pm.polymat_mul_batched(items, "fp64", ws=ws)
+        torch.cuda.synchronize()
+        pm.timing_enable(False)
+        ph = {k: round(v[0] / reps, 4) for k, v in pm.timing_read().items() if v[1]}
         res["points"].append({"ntrunc": nt, "naive_ms": round(t["naive"], 4), "fftconv_ms": round(t["fftconv"], 4),
-                              "naive_products": (nt + 1) * (nt + 2) // 2, "fft_modes": pm.transform_length(nt)})
+                              "naive_products": (nt + 1) * (nt + 2) // 2, "fft_modes": pm.transform_length(nt),
+                              "fftconv_phase_ms": ph,
+                              "in_chain_fftconv_ms": round(ph.get("forward", 0.0) + ph.get("product", 0.0)
+                                                           + ph.get("inverse", 0.0), 4)})
         del ws
     return res
 
