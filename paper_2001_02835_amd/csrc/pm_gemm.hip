@@ -49,14 +49,14 @@ GemmShape gemm_shape(FourierType t, int cfg) {
   return GemmShape{16 * sh.wm * sh.wgm, 16 * sh.wn * sh.wgn};
 }
 
-int gemm_config(FourierType t, int n) {
+int gemm_config(FourierType t, int n, int L) {
   if (t == kBF16Split) return 0;
   if (g_force_cfg >= 0 && g_force_cfg < kNumShapes) return g_force_cfg;
   const TuneRow* rows = t == kF64 ? kTune_fp64 : kTune_fp32;
   const int nrows = t == kF64 ? static_cast<int>(sizeof(kTune_fp64) / sizeof(TuneRow))
                               : static_cast<int>(sizeof(kTune_fp32) / sizeof(TuneRow));
   for (int i = 0; i < nrows; ++i)
-    if (n <= rows[i].n_max) return rows[i].cfg;
+    if (n <= rows[i].n_max && L <= rows[i].l_max) return rows[i].cfg;
   return rows[nrows - 1].cfg;
 }
 

@@ -95,7 +95,7 @@ struct GemmArgs { GemmJob jobs[kMaxGemmJobs]; int njobs; int total_tiles; };
 struct GemmShape { int bm, bn; };
 int gemm_num_configs(FourierType t);
 GemmShape gemm_shape(FourierType t, int cfg);
-int gemm_config(FourierType t, int n);          // tuned choice for matrix size n
+int gemm_config(FourierType t, int n, int L);   // tuned choice for matrix size n and transform length L
 bool gemm_uses_g3();                            // three-product complex form in use
 hipError_t launch_gemm(const GemmArgs& a, FourierType t, int cfg, hipStream_t s);
 // Direct convolution (eq. (5)) of FP64 time-domain series: job.L = ntrunc + 1

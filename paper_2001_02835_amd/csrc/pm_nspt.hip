@@ -167,8 +167,9 @@ struct GemmBatch {
   int cfg = 0;
   void add(const void* A, const void* B, void* C, int n, int L) {
     if (status) return;
-    if (a.njobs == kMaxGemmJobs) flush();
-    cfg = gemm_config(ft, n);      // one matrix size per NSPT call
+    const int c = gemm_config(ft, n, L);   // one matrix size per NSPT call; L per chain step
+    if (a.njobs == kMaxGemmJobs || (a.njobs > 0 && c != cfg)) flush();
+    cfg = c;
     const GemmShape sh = gemm_shape(ft, cfg);
     GemmJob& j = a.jobs[a.njobs++];
     j.A = A;

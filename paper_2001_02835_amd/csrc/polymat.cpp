@@ -267,7 +267,7 @@ pm_status enqueue_products(const std::vector<Planned>& items, int prec, hipStrea
           return s;
         };
         for (const Planned& it : items) {
-          if (it.pr.n != nsz || it.pr.op_a * 2 + it.pr.op_b != form || gemm_config(ft, it.pr.n) != cfg) continue;
+          if (it.pr.n != nsz || it.pr.op_a * 2 + it.pr.op_b != form || gemm_config(ft, it.pr.n, it.L) != cfg) continue;
           if (ga.njobs == kMaxGemmJobs) { pm_status s = flush(); if (s) return s; }
           GemmJob& j = ga.jobs[ga.njobs++];
           j.A = it.ws + it.lay.At;

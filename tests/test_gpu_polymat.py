@@ -129,6 +129,25 @@ def test_batched_uneven_with_conjugated_operands():
         assert e.max() < TOL["fp64"], e
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,nt", [(121, 31), (130, 63), (100, 15)])
+def test_tuned_tile_shapes_per_length(prec, n, nt):
+    """Sizes and transform lengths (L = 32, 64, 128) where the tile table
+    may pick a shape other than the default one (FP32 at 93 <= n <= 145 and
+    L >= 64), all four operand forms."""
+    items, refs = [], []
+    for i in range(4):
+        a, b = rs(130 + i, n, nt, 0.7), rs(140 + i, n, nt, 0.7)
+        op_a, op_b = i % 2, i // 2
+        refs.append(ser.star(ser.dagger(a) if op_a else a, ser.dagger(b) if op_b else b))
+        items.append(dict(A=to_dev(a), B=to_dev(b), C=torch.empty((nt + 1, n, n), dtype=torch.complex128, device=DEV),
+                          op_a=op_a, op_b=op_b, scale=0.0))
+    pm.polymat_mul_batched(items, precision=prec)
+    for i, (it, ref) in enumerate(zip(items, refs)):
+        e = order_errors(to_host(it["C"]), ref)
+        assert e.max() < TOL[prec], (i, e)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("n", [17, 33, 81, 161, 193, 225, 289])
 def test_thin_edge_sizes_all_operand_forms(prec, n):
