@@ -23,6 +23,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -38,11 +39,21 @@ HBM_PEAK_GBS = 8000.0
 GEMM_SOURCES = ("pm_gemm_impl.h", "pm_gemm_f64.hip", "pm_gemm.hip", "pm_gemm_tuning.h", "pm_common.h")
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and blank lines (comment edits leave the
+    compiled kernel and its counters unchanged)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(l.rstrip() for l in text.splitlines() if l.strip())
+
+
 def gemm_source_hash() -> str:
-    """Hash of the sources that define the FP64 product kernel and its shape choice."""
+    """Hash of the code (comments stripped) that defines the FP64 product
+    kernel and its shape choice."""
     h = hashlib.sha256()
     for name in GEMM_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2001_02835_amd", "csrc", name), "rb").read())
+        with open(os.path.join(ROOT, "paper_2001_02835_amd", "csrc", name)) as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -9,8 +9,9 @@
 // the transform of X^+ at mode p is (Xt^(-p))^+, so X^+ costs no extra pass.
 //
 // Coefficients are interleaved complex (re, im) in FP64 or FP32, unpadded
-// N x N row-major per mode.  A complex product is four real MFMA products
-// (re*re - im*im, re*im + im*re).  One work-group computes a BM x BN tile of
+// N x N row-major per mode.  A complex product is three real MFMA products
+// in the Gauss form (four, re*re - im*im and re*im + im*re, when selected;
+// see G3 below).  One work-group computes a BM x BN tile of
 // one mode with WGM x WGN wavefronts of WM x WN 16x16 blocks each; K is
 // staged through double-buffered LDS in chunks of 16.  Ragged edges are
 // zero-filled on load; whole 16x16 blocks and whole k-steps of 4 that lie
