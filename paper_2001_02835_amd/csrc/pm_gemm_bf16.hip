@@ -93,42 +93,47 @@ __device__ __forceinline__ void split_planes(const uint4 (&q)[4], uint4 (&pl)[4]
 // are never written, so k >= n is masked inside a vector too).
 template <bool KC>
 struct TileOp {
+  // Staging registers of one operand tile: the thread's 8 entries as loaded
+  // (the planes are separated only when they are stored to LDS, so that the
+  // loads of the next chunk stay in flight during this chunk's products).
+  struct Raw {
+    uint4 q[4];
+    int valid;      // entries of the run inside the matrix (<= 0: none)
+  };
+
   __device__ static __forceinline__ void load(const uint2* base, int ld, int n, int row0, int k0, int tid,
-                                              bool conj, uint4 (&r)[kVecs]) {
-    int gr, gk, valid;
-    size_t off;
+                                              Raw& r) {
+    int gr, gk;
     if constexpr (KC) {
       const int row = tid >> 2, kc = tid & 3;     // 64 rows x 4 runs of 8 k
       gr = row0 + row;
       gk = k0 + 8 * kc;
-      off = static_cast<size_t>(gr) * ld + gk;
-      valid = n - gk;
+      r.valid = n - gk;
     } else {
       const int kk = tid >> 3, rc = tid & 7;      // 32 k x 8 runs of 8 rows
       gk = k0 + kk;
       gr = row0 + 8 * rc;
-      off = static_cast<size_t>(gk) * ld + gr;
-      valid = n - gr;
+      r.valid = n - gr;
     }
-    if (gr < n && gk < n) {
-      const uint4* src = reinterpret_cast<const uint4*>(base + off);
-      uint4 q[4];
+    const bool ok = gr < n && gk < n;
+    if (!ok) r.valid = 0;
+    // a run outside the matrix reads entry 0 (always present) and is zeroed
+    // at the store; the loads carry no branch
+    const size_t off = ok ? (KC ? static_cast<size_t>(gr) * ld + gk : static_cast<size_t>(gk) * ld + gr) : 0;
+    const uint4* src = reinterpret_cast<const uint4*>(base + off);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) q[t] = src[t];
-      split_planes(q, r);
-#pragma unroll
-      for (int pl = 0; pl < 4; ++pl) r[pl] = mask_tail(r[pl], valid);
-      if (conj) {
-        r[2] = flip_sign(r[2]);
-        r[3] = flip_sign(r[3]);
-      }
-    } else {
-#pragma unroll
-      for (int pl = 0; pl < 4; ++pl) r[pl] = make_uint4(0, 0, 0, 0);
-    }
+    for (int t = 0; t < 4; ++t) r.q[t] = src[t];
   }
 
-  __device__ static __forceinline__ void store(uint16_t* tile, int tid, const uint4 (&r)[kVecs]) {
+  __device__ static __forceinline__ void store(uint16_t* tile, int tid, const Raw& raw, bool conj) {
+    uint4 r[kVecs];
+    split_planes(raw.q, r);
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) r[pl] = raw.valid > 0 ? mask_tail(r[pl], raw.valid) : make_uint4(0, 0, 0, 0);
+    if (conj) {
+      r[2] = flip_sign(r[2]);
+      r[3] = flip_sign(r[3]);
+    }
 #pragma unroll
     for (int pl = 0; pl < 4; ++pl) {
       uint16_t* p = tile + pl * kPlaneElems;
@@ -214,18 +219,18 @@ __global__ __launch_bounds__(kThreadsB, 3) void k_cgemm_bf16x3(GemmArgs args) {
 #pragma unroll
   for (int b = 0; b < 2; ++b) nact[b] = col0 + wcol0 + 16 * b < n;
 
-  uint4 ra[kVecs], rb[kVecs];
+  typename TA::Raw ra;
+  typename TB::Raw rb;
   const int nk = (n + kBK - 1) / kBK;
-  TA::load(Ab, ld, n, row0, 0, tid, OPA, ra);
-  TB::load(Bb, ld, n, col0, 0, tid, OPB, rb);
+  TA::load(Ab, ld, n, row0, 0, tid, ra);
+  TB::load(Bb, ld, n, col0, 0, tid, rb);
   for (int c = 0; c < nk; ++c) {
-    TA::store(As, tid, ra);
-    TB::store(Bs, tid, rb);
+    TA::store(As, tid, ra, OPA);
+    TB::store(Bs, tid, rb, OPB);
     __syncthreads();
-    if (c + 1 < nk) {
-      TA::load(Ab, ld, n, row0, (c + 1) * kBK, tid, OPA, ra);
-      TB::load(Bb, ld, n, col0, (c + 1) * kBK, tid, OPB, rb);
-    }
+    // the next chunk's loads (past the end: a chunk of zeros, still in bounds)
+    TA::load(Ab, ld, n, row0, (c + 1) * kBK, tid, ra);
+    TB::load(Bb, ld, n, col0, (c + 1) * kBK, tid, rb);
     uint4 fb[2][4];
 #pragma unroll
     for (int b = 0; b < 2; ++b)
