@@ -144,6 +144,29 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return base + local;
 }
 
+// Tile (tm, tn) of the rem-th work-group of one mode of an n x n product
+// cut into tiles_m x tiles_n tiles of bm x bn: the full tiles first (row by
+// row), then the right edge, the bottom edge and the corner, so that the
+// shorter tiles of a launch are dispatched after the longer ones.
+__device__ __forceinline__ void tile_in_mode(int rem, int n, int tiles_m, int tiles_n, int bm, int bn, int& tm,
+                                             int& tn) {
+  const int fm = (n % bm == 0) ? tiles_m : tiles_m - 1;   // full tile rows
+  const int fn = (n % bn == 0) ? tiles_n : tiles_n - 1;   // full tile columns
+  if (rem < fm * fn) {
+    tm = rem / fn;
+    tn = rem - tm * fn;
+    return;
+  }
+  int r2 = rem - fm * fn;
+  if (fn < tiles_n) {
+    if (r2 < fm) { tm = r2; tn = tiles_n - 1; return; }
+    r2 -= fm;
+  }
+  if (fm < tiles_m && r2 < fn) { tm = tiles_m - 1; tn = r2; return; }
+  tm = tiles_m - 1;
+  tn = tiles_n - 1;
+}
+
 // ------------------------------------------------------------- job tables
 
 // Scale record of one product (device memory, written by the scale kernel):

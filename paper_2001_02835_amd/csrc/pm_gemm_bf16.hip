@@ -190,8 +190,8 @@ __global__ __launch_bounds__(kThreadsB, 3) void k_cgemm_bf16x3(GemmArgs args) {
   const int per_mode = jb.tiles_m * jb.tiles_n;
   const int p = local / per_mode;
   const int rem = local - p * per_mode;
-  const int tm = rem / jb.tiles_n;
-  const int tn = rem - tm * jb.tiles_n;
+  int tm, tn;
+  tile_in_mode(rem, jb.n, jb.tiles_m, jb.tiles_n, kBM, kBM, tm, tn);
   const int n = jb.n, L = jb.L;
   const int ld = bf16_ld(n);
   const size_t mode = static_cast<size_t>(n) * ld;

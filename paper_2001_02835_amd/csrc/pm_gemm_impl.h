@@ -462,9 +462,8 @@ __device__ __forceinline__ void cgemm2_tile(const GemmJob& jb, int p, int tm, in
 }
 
 // Decode a logical GEMM task id into (job, mode, tile row, tile column) for
-// BM x BN tiles.  Within a mode the full tiles come first, then the right
-// edge, the bottom edge and the corner, so that the shorter tiles of a launch
-// are dispatched after the longer ones (about 1 % faster at N = 225).
+// BM x BN tiles, the shorter tiles of a mode last (tile_in_mode; about 1 %
+// faster at N = 225).
 __device__ __forceinline__ void gemm_task(const GemmJob* jobs, int njobs, int id, int bm, int bn, int& jidx, int& p,
                                           int& tm, int& tn) {
   jidx = 0;
@@ -475,21 +474,7 @@ __device__ __forceinline__ void gemm_task(const GemmJob* jobs, int njobs, int id
   const int per_mode = jb.tiles_m * jb.tiles_n;
   p = local / per_mode;
   const int rem = local - p * per_mode;
-  const int fm = (jb.n % bm == 0) ? jb.tiles_m : jb.tiles_m - 1;   // full tile rows
-  const int fn = (jb.n % bn == 0) ? jb.tiles_n : jb.tiles_n - 1;   // full tile columns
-  if (rem < fm * fn) {
-    tm = rem / fn;
-    tn = rem - tm * fn;
-    return;
-  }
-  int r2 = rem - fm * fn;
-  if (fn < jb.tiles_n) {
-    if (r2 < fm) { tm = r2; tn = jb.tiles_n - 1; return; }
-    r2 -= fm;
-  }
-  if (fm < jb.tiles_m && r2 < fn) { tm = jb.tiles_m - 1; tn = r2; return; }
-  tm = jb.tiles_m - 1;
-  tn = jb.tiles_n - 1;
+  tile_in_mode(rem, jb.n, jb.tiles_m, jb.tiles_n, bm, bn, tm, tn);
 }
 
 template <typename T, int WM, int WN, int WGM, int WGN, bool OPA, bool OPB, bool G3, bool CONV = false>
