@@ -121,13 +121,26 @@ def bench_uneven(torch, synth, pm, dev, steps):
         items.append(dict(A=a, B=b, C=torch.empty_like(a), scale=0.0))
     useful = sum(pm.transform_length(nt) * 8.0 * n ** 3 for n, nt in shapes)
     res = {"workload": "64 products, N in {64,121,169,225,289}, ntrunc in {15,31,63}, entries N(0,1)*0.7^k, "
-                       "one batched call", "useful_gflop_per_batch": round(useful / 1e9, 1)}
+                       "one batched call (staged launches: norms, scale, forward per transform length, products "
+                       "per matrix size, inverse per transform length)",
+           "useful_gflop_per_batch": round(useful / 1e9, 1)}
     for prec in ("fp64", "bf16x3"):
         ws = pm.workspace(pm.batched_workspace_size(items, prec), dev)
         ms, ph = time_steps(torch, pm, items, prec, steps, 1, ws, timing=True)
         res[prec] = {"ms_per_batch": round(ms, 3), "mults_per_s": round(64 / (ms * 1e-3), 1),
                      "useful_tflops": round(useful / (ms * 1e-3) / 1e12, 2),
                      "phase_ms_per_batch": {k: round(v[0] / steps, 3) for k, v in ph.items() if v[1]}}
+        if prec == "fp64":
+            # the same batch through the opt-in persistent one-launch pipeline
+            # (set-up launches, then every step of every product in one launch)
+            os.environ["POLYMAT_PIPELINE"] = "1"
+            try:
+                pms, _ = time_steps(torch, pm, items, prec, steps, 1, ws)
+            finally:
+                del os.environ["POLYMAT_PIPELINE"]
+            res["fp64_one_launch_pipeline"] = {"ms_per_batch": round(pms, 3),
+                                               "useful_tflops": round(useful / (pms * 1e-3) / 1e12, 2),
+                                               "note": "opt-in (POLYMAT_PIPELINE=1); the staged launches are the default"}
         del ws
     return res
 
