@@ -148,7 +148,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 // cut into tiles_m x tiles_n tiles of bm x bn: the full tiles first (row by
 // row), then the right edge, the bottom edge and the corner, so that the
 // shorter tiles of a launch are dispatched after the longer ones.
-__device__ __forceinline__ void tile_in_mode(int rem, int n, int tiles_m, int tiles_n, int bm, int bn, int& tm,
+__host__ __device__ __forceinline__ void tile_in_mode(int rem, int n, int tiles_m, int tiles_n, int bm, int bn, int& tm,
                                              int& tn) {
   const int fm = (n % bm == 0) ? tiles_m : tiles_m - 1;   // full tile rows
   const int fn = (n % bn == 0) ? tiles_n : tiles_n - 1;   // full tile columns
