@@ -7,7 +7,9 @@ per link direction, with N = 225 (SU(225)), ntrunc = 31 (orders g^0..g^31,
 transform length 64), complex128 coefficients with i.i.d. N(0,1) real and
 imaginary parts times 0.5^k at order k, FP64 mode-wise products, rescaling
 chosen on the device.  Inputs are resident in HBM before the timed region.
-The value is products per second over the K timed steps.
+The value is products per second over the K timed steps, which run after the
+other workloads of the line (the GPU at its running clock); the same W + K
+steps timed right after start-up are reported as cold_start.
 
 Also reported: the same metric at ntrunc = 63 (N = 225, entries times 1.3^k)
 for the FP64, FP32 and split-BF16 product precisions, the time per phase,
