@@ -171,7 +171,17 @@ __device__ __forceinline__ int lane_mode(int q, int lane) {
 // acc[k][el] <- sum_p Ct[p] w^{-kp} for all k < L/2 (no 1/L), from the modes
 // d[q] = Ct[lane_mode<L,R>(q)] of this lane (d is overwritten).  Ends with a
 // barrier, after which every wavefront may read acc.
-template <int L, int R, int S = fft_split<L>()>
+//
+// One lane per entry: the four residues are summed into acc in four phases
+// separated by barriers.  Chained (ROT = false), wavefront r writes or adds
+// all rows in phase r while the other three wait.  Rotated (ROT = true, L >= 8),
+// every wavefront works in every phase: in phase p wavefront r adds its terms
+// to row block (r + p) mod 4 (a quarter of the rows), so block b receives
+// the residues b, b-1, b-2, b-3 in that order.  Both orders are fixed, so the
+// results are bitwise reproducible.  The rotated form is faster for the
+// stand-alone inverse and the re-truncation of FP32 products, slower for the
+// weighted-sum inverse and the re-truncation of FP64 products (measured).
+template <int L, int R, int S = fft_split<L>(), bool ROT = false>
 __device__ __forceinline__ void inverse_from_modes(double2* d, double2 (*acc)[kEnt / S], int lane) {
   constexpr int M = L / 4;
   constexpr int ENT = kEnt / S;
@@ -182,15 +192,28 @@ __device__ __forceinline__ void inverse_from_modes(double2* d, double2 (*acc)[kE
       constexpr int k = decltype(ki)::value;
       return ctwiddle<k * R, L, -1>(d[k % M]);
     };
-    // fixed order: r = 0 writes, r = 1, 2, 3 add
-    for (int w = 0; w < 4; ++w) {
-      if (w == R) {
-        static_for<0, 2 * M>([&](auto ki) {
+    if constexpr (ROT && (2 * M) % 4 == 0) {
+      constexpr int QB = 2 * M / 4;   // rows per block
+      static_for<0, 4>([&](auto pi) {
+        constexpr int p = decltype(pi)::value;
+        constexpr int b = (R + p) & 3;
+        static_for<b * QB, (b + 1) * QB>([&](auto ki) {
           constexpr int k = decltype(ki)::value;
-          acc[k][lane] = (R == 0) ? term(ki) : cadd(acc[k][lane], term(ki));
+          acc[k][lane] = (p == 0) ? term(ki) : cadd(acc[k][lane], term(ki));
         });
+        __syncthreads();
+      });
+    } else {
+      // fixed order: r = 0 writes, r = 1, 2, 3 add
+      for (int w = 0; w < 4; ++w) {
+        if (w == R) {
+          static_for<0, 2 * M>([&](auto ki) {
+            constexpr int k = decltype(ki)::value;
+            acc[k][lane] = (R == 0) ? term(ki) : cadd(acc[k][lane], term(ki));
+          });
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
   } else {
     // half h holds the length-M/2 inverse DFT of the even (h = 0) or odd
@@ -231,7 +254,7 @@ __device__ __forceinline__ void inverse_from_modes(double2* d, double2 (*acc)[kE
 }
 
 // Same, where load(p) returns mode p of this thread's entry.
-template <int L, int R, int S, typename Load>
+template <int L, int R, int S, bool ROT, typename Load>
 __device__ __forceinline__ void inverse_residue(Load&& load, double2 (*acc)[kEnt / S], int lane) {
   constexpr int NQ = lane_nmodes<L, S>();
   double2 d[NQ];
@@ -239,16 +262,16 @@ __device__ __forceinline__ void inverse_residue(Load&& load, double2 (*acc)[kEnt
     constexpr int q = decltype(qi)::value;
     d[q] = load(lane_mode<L, R, S>(q, lane));
   });
-  inverse_from_modes<L, R, S>(d, acc, lane);
+  inverse_from_modes<L, R, S, ROT>(d, acc, lane);
 }
 
-template <int L, int S = fft_split<L>(), typename Load>
+template <int L, int S = fft_split<L>(), bool ROT = false, typename Load>
 __device__ __forceinline__ void inverse_to_lds(Load&& load, double2 (*acc)[kEnt / S], int lane, int r) {
   switch (r) {
-    case 0: inverse_residue<L, 0, S>(load, acc, lane); break;
-    case 1: inverse_residue<L, 1, S>(load, acc, lane); break;
-    case 2: inverse_residue<L, 2, S>(load, acc, lane); break;
-    default: inverse_residue<L, 3, S>(load, acc, lane); break;
+    case 0: inverse_residue<L, 0, S, ROT>(load, acc, lane); break;
+    case 1: inverse_residue<L, 1, S, ROT>(load, acc, lane); break;
+    case 2: inverse_residue<L, 2, S, ROT>(load, acc, lane); break;
+    default: inverse_residue<L, 3, S, ROT>(load, acc, lane); break;
   }
 }
 

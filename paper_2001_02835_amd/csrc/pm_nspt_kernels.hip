@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kFftThreads, fft_min_waves<LOUT>()) void k_retrunc(
   const int nord = jb.nord;
   if (jb.src) {
     auto load = [&](int p) { return valid ? load_mode<FIN>(jb.src, E, p, e) : make_double2(0.0, 0.0); };
-    inverse_to_lds<LIN>(load, acc, lane, r);
+    inverse_to_lds<LIN, fft_split<LIN>(), FIN == kF32>(load, acc, lane, r);
   }
   // time-domain value of order k: (1/L) inverse + addends (+ identity at order 0)
   const int n = jb.n;

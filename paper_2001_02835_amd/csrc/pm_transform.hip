@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kFftThreads, (inverse_min_waves<L, FT>())) void k_i
   const int e = e0 + el;
   const bool valid = e < jb.E;
   auto load = [&](int p) { return valid ? load_mode<FT>(jb.src, jb.E, p, e) : make_double2(0.0, 0.0); };
-  inverse_to_lds<L>(load, acc, lane, r);
+  inverse_to_lds<L, fft_split<L>(), true>(load, acc, lane, r);
   // Steps 4-5: 1/L, unscale by s^-k (one table), keep orders < nord
   if (valid) {
     bool bad = false;
