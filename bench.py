@@ -504,10 +504,17 @@ def main(argv=None):
         # the crossover's single small products leave the GPU idle between
         # calls, so it runs before the long workloads; the MD trajectory, the
         # longest, comes right before the headline
-        crossover = bench_crossover(torch, synth, pm, dev)
-        extras["batched_uneven"] = bench_uneven(torch, synth, pm, dev, max(args.steps // 20, 3))
-        extras["nspt_step"] = bench_nspt(torch, synth, pm, dev, args.nspt_steps)
-        extras["nspt_md"] = bench_md(torch, synth, pm, dev, args.md_steps)
+        def guarded(fn, *a):
+            # an extra line that fails reports its error; the headline still runs
+            try:
+                return fn(*a)
+            except Exception as exc:
+                torch.cuda.synchronize()
+                return {"error": str(exc)}
+        crossover = guarded(bench_crossover, torch, synth, pm, dev)
+        extras["batched_uneven"] = guarded(bench_uneven, torch, synth, pm, dev, max(args.steps // 20, 3))
+        extras["nspt_step"] = guarded(bench_nspt, torch, synth, pm, dev, args.nspt_steps)
+        extras["nspt_md"] = guarded(bench_md, torch, synth, pm, dev, args.md_steps)
         extras["naive_vs_fftconv"] = crossover
 
     # ---- headline, timed after the other workloads (the GPU at its running
